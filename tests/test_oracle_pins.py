@@ -1,0 +1,401 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names what pins it: a closed form (Sylvester Hadamard matrices), the
+published SplitMix64 outputs, an invariant the paper states (Algorithm 1:
+iProbes buckets per point, alpha*n points per table; Section 4: Falconn is
+Falconn++ with alpha = 1 and iProbes = 1), a special case (full probing reaches every
+sign-consistent point), a library routine (scipy's Hadamard, torch's bf16 / fp8 casts)
+or brute-force enumeration on tiny inputs written with Python loops.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import falconn as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ signs
+def test_splitmix64_published_outputs():
+    vals = [int(l) for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+            if l.strip() and not l.startswith("#")]
+    got = [int(v) for v in O.splitmix64_at(1234567, np.arange(5))]
+    assert got == vals
+
+
+def test_signs_balanced_and_seeded():
+    S = O.rotation_signs(7, 4, 2, 256)
+    assert S.shape == (4, 2, 3, 256)
+    assert set(np.unique(S)) == {-1, 1}
+    frac = np.mean(S == -1)
+    assert abs(frac - 0.5) < 5 * 0.5 / math.sqrt(S.size)
+    assert not np.array_equal(S, O.rotation_signs(8, 4, 2, 256))
+    np.testing.assert_array_equal(S, O.rotation_signs(7, 4, 2, 256))
+
+
+# ------------------------------------------------------------------ transform
+@pytest.mark.parametrize("P", [2, 4, 8, 16, 64, 128, 512])
+def test_fwht_equals_sylvester_matrix(P):
+    rng = np.random.default_rng(P)
+    V = rng.integers(-50, 51, size=(5, P)).astype(np.float32)   # exact in float32
+    H = scipy.linalg.hadamard(P).astype(np.float64)
+    np.testing.assert_array_equal(O.fwht_f32(V).astype(np.float64), V.astype(np.float64) @ H)
+
+
+@pytest.mark.parametrize("P", [4, 64, 256, 4096])
+def test_fwht_twice_is_P_identity(P):
+    rng = np.random.default_rng(1)
+    V = rng.integers(-8, 9, size=(3, P)).astype(np.float32)
+    np.testing.assert_array_equal(O.fwht_f32(O.fwht_f32(V)), V * np.float32(P))
+
+
+def test_fwht_preserves_norm_up_to_P():
+    rng = np.random.default_rng(2)
+    V = rng.standard_normal((20, 256)).astype(np.float32)
+    W = O.fwht_f32(V).astype(np.float64)
+    r = (W ** 2).sum(1) / (256.0 * (V.astype(np.float64) ** 2).sum(1))
+    np.testing.assert_allclose(r, 1.0, rtol=1e-6)
+
+
+def _rotation_matrix(signs_f, P):
+    H = scipy.linalg.hadamard(P).astype(np.float64)
+    R = np.eye(P)
+    for r in range(3):
+        R = H @ np.diag(signs_f[r].astype(np.float64)) @ R
+    return R
+
+
+@pytest.mark.parametrize("P", [8, 64, 256])
+def test_rotation_is_scaled_orthogonal(P):
+    S = O.rotation_signs(3, 1, 1, P)[0, 0]
+    R = _rotation_matrix(S, P)
+    np.testing.assert_array_equal(R.T @ R, (P ** 3) * np.eye(P))
+    # the oracle's rotation applied to basis vectors reproduces the explicit product
+    Y = O.rotate(np.eye(P, dtype=np.float32), S, P).astype(np.float64)
+    np.testing.assert_array_equal(Y, R.T)   # row j of Y is R e_j
+
+
+def test_rotation_matches_explicit_product_with_padding():
+    d, D = 50, 64
+    S = O.rotation_signs(11, 1, 1, 64)[0, 0]
+    R = _rotation_matrix(S, 64)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((10, d)).astype(np.float32)
+    Xp = np.zeros((10, 64))
+    Xp[:, :d] = X
+    ref = Xp @ R.T
+    got = O.rotate(X, S, D).astype(np.float64)
+    assert np.max(np.abs(got - ref)) < 1e-5 * np.max(np.abs(ref))
+
+
+# ------------------------------------------------------------------ code rule (Eq. 1)
+def _preimage(S, P, v):
+    """x with R x = v exactly: x = R^T v / P^3 (R has integer entries, P^3 a power of two)."""
+    R = _rotation_matrix(S, P)
+    x = (R.T @ v) / float(P ** 3)
+    assert np.array_equal(x.astype(np.float32).astype(np.float64), x)
+    return x.astype(np.float32)[None, :]
+
+
+@pytest.mark.parametrize("P", [16, 64])
+def test_code_of_basis_preimages(P):
+    S = O.rotation_signs(5, 1, 1, P)
+    for i in range(P):
+        e = np.zeros(P)
+        e[i] = 1.0
+        assert O.hash_codes(_preimage(S[0, 0], P, e), S, P)[0, 0, 0] == i
+        assert O.hash_codes(_preimage(S[0, 0], P, -e), S, P)[0, 0, 0] == i + P
+
+
+def test_code_tie_rule_and_zero_vector():
+    P = 16
+    S = O.rotation_signs(9, 1, 1, P)
+    code = lambda v: O.hash_codes(_preimage(S[0, 0], P, np.asarray(v, float)), S, P)[0, 0, 0]
+    e = np.eye(P)
+    assert code(e[3] + e[7]) == 3            # tie -> smaller index, positive -> +r
+    assert code(-e[3] + e[7]) == 3 + P       # tie -> smaller index, negative -> -r
+    assert code(e[3] - 2 * e[7]) == 7 + P
+    assert O.hash_codes(np.zeros((1, P), np.float32), S, P)[0, 0, 0] == 0
+
+
+# ------------------------------------------------------------------ index (Algorithm 1)
+def _brute_top_pairs(X, signs_t, D, K):
+    """All D^2 pairs scored from the raw projections with Python loops (reading R5)."""
+    out = []
+    y = [O.rotate(X, signs_t[f], D) for f in range(2)]
+    for p in range(X.shape[0]):
+        ranks = []
+        for f in range(2):
+            order = sorted(range(D), key=lambda i: (-abs(float(y[f][p, i])), i))
+            ranks.append({i: r for r, i in enumerate(order)})
+        cands = []
+        for i in range(D):
+            for j in range(D):
+                s = np.float32(abs(y[0][p, i])) + np.float32(abs(y[1][p, j]))
+                c1 = i if y[0][p, i] >= 0 else i + D
+                c2 = j if y[1][p, j] >= 0 else j + D
+                cands.append((-float(np.float32(s)), ranks[0][i], ranks[1][j], c1 * 2 * D + c2))
+        cands.sort()
+        out.append([c[3] for c in cands[:K]])
+    return out
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5, 10])
+def test_top_pairs_equal_full_enumeration(K):
+    rng = np.random.default_rng(K)
+    X = rng.standard_normal((60, 8)).astype(np.float32)
+    D = 8
+    S = O.rotation_signs(21, 1, 2, 8)[0]
+    lists = [O.hash_lists(X, S[f], D) for f in range(2)]
+    b, key = O.top_pairs(lists, D, K)
+    assert b.tolist() == _brute_top_pairs(X, S, D, K)
+    assert np.all(np.diff(key, axis=1) <= 0)
+
+
+def test_top_pairs_with_exact_ties():
+    # zero vectors: every pair scores 0, the position tie-break decides
+    D = 8
+    S = O.rotation_signs(1, 1, 2, 8)[0]
+    X = np.zeros((2, 8), np.float32)
+    lists = [O.hash_lists(X, S[f], D) for f in range(2)]
+    b, _ = O.top_pairs(lists, D, 4)
+    assert b.tolist() == _brute_top_pairs(X, S, D, 4)
+
+
+def test_each_point_in_exactly_iprobes_distinct_buckets():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((500, 32)).astype(np.float32)
+    S = O.rotation_signs(2, 1, 2, 32)[0]
+    lists = [O.hash_lists(X, S[f], 32) for f in range(2)]
+    for K in (1, 3, 7):
+        b, _ = O.top_pairs(lists, 32, K)
+        assert b.shape == (500, K)
+        assert all(len(set(row)) == K for row in b.tolist())
+        assert b.min() >= 0 and b.max() < 64 * 64
+
+
+def test_keep_count_values():
+    k = lambda B, a, ip: int(O.keep_count(np.array([B]), a, ip)[0])
+    assert k(10, 0.3, 3) == 1 and k(11, 0.3, 3) == 2 and k(0, 0.3, 3) == 0
+    assert k(1, 0.5, 1) == 1 and k(2, 0.5, 1) == 1 and k(3, 0.5, 1) == 2
+    assert k(7, 1.0, 1) == 7 and k(1, 0.01, 3) == 1
+    assert int(O.keep_count(np.array([301]), 0.01, 1, "floor")[0]) == 3
+
+
+def _uniform_data(n, d, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, d))
+    return (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+
+
+@pytest.mark.parametrize("l", [1, 2])
+def test_alpha1_iprobes1_is_a_partition_by_home_bucket(l):
+    """Section 4: Falconn is Falconn++ with iProbes = 1 and alpha = 1."""
+    X = _uniform_data(700, 24, 5)
+    D = 16
+    idx = O.build_index(X, L=3, D=D, alpha=1.0, iProbes=1, seed=13, l=l)
+    codes = O.hash_codes(X, idx.signs, D)
+    for t in range(3):
+        ids = idx.ids[t]
+        assert sorted(ids.tolist()) == list(range(700))
+        home = codes[:, t, 0] if l == 1 else codes[:, t, 0] * (2 * D) + codes[:, t, 1]
+        off = idx.offsets[t]
+        for b in np.nonzero(np.diff(off))[0]:
+            assert np.all(home[ids[off[b]:off[b + 1]]] == b)
+
+
+@pytest.mark.parametrize("alpha,iprobes", [(0.3, 3), (0.5, 1), (0.1, 2)])
+def test_filter_matches_per_bucket_brute_force(alpha, iprobes):
+    X = _uniform_data(400, 16, 6)
+    D = 8
+    idx = O.build_index(X, L=2, D=D, alpha=alpha, iProbes=iprobes, seed=3, l=2)
+    for t in range(2):
+        lists = [O.hash_lists(X, idx.signs[t, f], D) for f in range(2)]
+        b, key = O.top_pairs(lists, D, iprobes)
+        buckets = {}
+        for p in range(400):
+            for r in range(iprobes):
+                buckets.setdefault(int(b[p, r]), []).append((-float(key[p, r]), p))
+        off, ids = idx.offsets[t], idx.ids[t]
+        total = 0
+        for bk in range(O.n_buckets(D, 2)):
+            recs = sorted(buckets.get(bk, []))
+            B = len(recs)
+            keep = math.ceil(round(alpha * 1e6) * B / (iprobes * 1e6) - 1e-12) if B else 0
+            assert off[bk + 1] - off[bk] == keep
+            assert ids[off[bk]:off[bk + 1]].tolist() == [p for _, p in recs[:keep]]
+            total += keep
+        nonempty = len(buckets)
+        assert alpha * 400 - 1e-9 <= total <= alpha * 400 + nonempty
+
+
+# ------------------------------------------------------------------ query
+def _brute_probes(idx, q, qProbes):
+    D, L = idx.D, idx.L
+    cands = []
+    for t in range(L):
+        y = [O.rotate(q[None, :], idx.signs[t, f], D)[0] for f in range(2)]
+        ranks = []
+        for f in range(2):
+            order = sorted(range(D), key=lambda i: (-abs(float(y[f][i])), i))
+            ranks.append({i: r for r, i in enumerate(order)})
+        for i in range(D):
+            for j in range(D):
+                s = float(np.float32(np.float32(abs(y[0][i])) + np.float32(abs(y[1][j]))))
+                c1 = i if y[0][i] >= 0 else i + D
+                c2 = j if y[1][j] >= 0 else j + D
+                cands.append((-s, t, ranks[0][i], ranks[1][j], t * 4 * D * D + c1 * 2 * D + c2))
+    cands.sort()
+    return [c[4] for c in cands[:qProbes]]
+
+
+@pytest.mark.parametrize("qProbes", [1, 5, 37, 10_000])
+def test_probe_ranking_equals_enumeration(qProbes):
+    X = _uniform_data(50, 12, 7)
+    idx = O.build_index(X, L=3, D=4, alpha=0.5, iProbes=2, seed=5, l=2)
+    q = _uniform_data(1, 12, 8)[0]
+    assert O.probes(idx, q, qProbes).tolist() == _brute_probes(idx, q, qProbes)
+
+
+def test_full_probing_reaches_every_sign_consistent_point():
+    """Probing all L * D^l pairs visits, per table, every bucket whose wedges lie on the query's
+    side of each random vector (Eq. 1 picks +r_i or -r_i by the sign of the projection). With
+    alpha = 1 and iProbes = 1 the candidates are exactly the points whose home bucket is such a
+    bucket in some table, and the answer is brute force over those points."""
+    X = _uniform_data(300, 20, 9)
+    Q = _uniform_data(15, 20, 10)
+    for l, D in ((1, 16), (2, 8)):
+        idx = O.build_index(X, L=2, D=D, alpha=1.0, iProbes=1, seed=1, l=l)
+        ids, sc, st = O.query(idx, Q, 10, qProbes=10 ** 9)
+        codes = O.hash_codes(X, idx.signs, D)
+        for r in range(Q.shape[0]):
+            members = []
+            for p in range(300):
+                hit = False
+                for t in range(2):
+                    ok = True
+                    for f in range(l):
+                        yq = O.rotate(Q[r:r + 1], idx.signs[t, f], D)[0]
+                        c = int(codes[p, t, f])
+                        ok = ok and ((c < D) == bool(yq[c % D] >= 0))
+                    hit = hit or ok
+                if hit:
+                    members.append(p)
+            assert st[r, 2] == len(members)
+            members = np.array(members, dtype=np.int64)
+            bi, bs = O.brute_force(X[members], Q[r:r + 1], 10)
+            ref = np.where(bi[0] >= 0, members[np.maximum(bi[0], 0)], -1)
+            assert ids[r].tolist() == ref.tolist()
+            np.testing.assert_array_equal(sc[r], bs[0])
+
+
+def test_brute_force_equals_enumeration():
+    X = _uniform_data(1500, 10, 11)
+    X[7] = X[3]          # a duplicate point: the id tie-break must apply
+    Q = _uniform_data(6, 10, 12)
+    Q[0] = X[3]
+    bi, bs = O.brute_force(X, Q, 12)
+    for r in range(6):
+        sc = [(-math.fsum(float(a) * float(b) for a, b in zip(X[i], Q[r])), i) for i in range(1500)]
+        sc.sort()
+        assert bi[r].tolist() == [i for _, i in sc[:12]]
+        np.testing.assert_allclose(bs[r], [-s for s, _ in sc[:12]], rtol=0, atol=1e-15)
+    assert bi[0, 0] == 3 and bi[0, 1] == 7
+
+
+def test_short_results_are_padded():
+    X = _uniform_data(5, 8, 13)
+    idx = O.build_index(X, L=1, D=8, alpha=1.0, iProbes=1, seed=2, l=1)
+    ids, sc, _ = O.query(idx, X[:1], 10, qProbes=1)
+    n_found = int((ids[0] >= 0).sum())
+    assert n_found >= 1 and np.all(ids[0, n_found:] == -1) and np.all(np.isneginf(sc[0, n_found:]))
+    assert ids[0, 0] == 0
+
+
+def test_recall():
+    t = np.array([[1, 2, 3, 4]])
+    assert O.recall_at_k(np.array([[4, 3, 9, -1]]), t) == 0.5
+    assert O.recall_at_k(t, t) == 1.0
+
+
+def test_lemma2_projection_on_argmax_vector_statistical():
+    """Loose sanity of Lemma 2 (CEOs): with r_i scaled to Gaussian length (rows of R have norm
+    P^{3/2}, a Gaussian vector about sqrt(P), so y / P), x^T r_1 has mean near rho * sqrt(2 ln D)."""
+    P = D = 1024
+    rng = np.random.default_rng(14)
+    S = O.rotation_signs(4, 200, 1, P)
+    rho = 0.8
+    vals = []
+    for t in range(200):
+        q = rng.standard_normal(P)
+        q /= np.linalg.norm(q)
+        z = rng.standard_normal(P)
+        z -= (z @ q) * q
+        z /= np.linalg.norm(z)
+        x = rho * q + math.sqrt(1 - rho ** 2) * z
+        yq = O.rotate(q[None].astype(np.float32), S[t, 0], D)[0].astype(np.float64)
+        yx = O.rotate(x[None].astype(np.float32), S[t, 0], D)[0].astype(np.float64)
+        i = int(np.argmax(np.abs(yq)))
+        vals.append(np.sign(yq[i]) * yx[i] / P)
+    mean = float(np.mean(vals))
+    # Lemma 2 is asymptotic in D; at D = 1024 the extreme-value mean sits below sqrt(2 ln D)
+    assert 0.75 * rho * math.sqrt(2 * math.log(D)) < mean < 1.05 * rho * math.sqrt(2 * math.log(D))
+
+
+# ------------------------------------------------------------------ quantisers
+def test_bf16_matches_torch_rne():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(15)
+    x = rng.standard_normal(20000).astype(np.float32)
+    # exact halfway cases: low 16 bits = 0x8000 with both parities of bit 16
+    u = rng.integers(0, 2 ** 31, 2000, dtype=np.uint64).astype(np.uint32)
+    u = (u & np.uint32(0x7F7F0000)) | np.uint32(0x8000)
+    x = np.concatenate([x, u.view(np.float32), -u.view(np.float32), [0.0, -0.0]]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    np.testing.assert_array_equal(O.bf16_bits(x), ref)
+
+
+def test_e4m3_matches_torch_and_table():
+    torch = pytest.importorskip("torch")
+    if not hasattr(torch, "float8_e4m3fn"):
+        pytest.skip("torch without float8_e4m3fn")
+    rng = np.random.default_rng(16)
+    vals = O.e4m3_value(np.arange(127, dtype=np.uint8)).astype(np.float64)
+    mids = (vals[:-1] + vals[1:]) / 2
+    x = np.concatenate([rng.uniform(-448, 448, 20000), vals, -vals, mids, -mids,
+                        rng.uniform(-0.02, 0.02, 5000)]).astype(np.float32)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    np.testing.assert_array_equal(O.e4m3_bits(x), ref)
+    # decode: torch's widening cast of every finite code
+    codes = np.array([c for c in range(256) if (c & 0x7F) != 0x7F], dtype=np.uint8)
+    dec = torch.from_numpy(codes).view(torch.float8_e4m3fn).to(torch.float32).numpy()
+    np.testing.assert_array_equal(O.e4m3_value(codes), dec)
+    assert O.e4m3_value(np.array([0x7E], np.uint8))[0] == 448.0
+    assert O.e4m3_bits(np.array([1000.0, -1e6], np.float32)).tolist() == [0x7E, 0xFE]
+
+
+def test_fp8_rows_scale_and_zero_vector():
+    X = _uniform_data(50, 33, 17)
+    X[4] = 0.0
+    codes, s = O.quantize_fp8_rows(X)
+    assert s[4] == 1.0 and np.all(codes[4] == 0)
+    mx = np.max(np.abs(O.e4m3_value(codes)), axis=1)
+    assert np.all(mx[np.arange(50) != 4] == 448.0)
+    deq = O.dequantized_store(X, "fp8")
+    rel = np.abs(deq - X) / np.max(np.abs(X), axis=1, keepdims=True).clip(1e-30)
+    assert rel[np.arange(50) != 4].max() <= 2.0 ** -4 * 1.0001   # half an ulp at the top binade
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_rerank_with_full_short_list_equals_plain_query(storage):
+    X = _uniform_data(400, 16, 18)
+    Q = _uniform_data(8, 16, 19)
+    idx = O.build_index(X, L=4, D=8, alpha=0.5, iProbes=2, seed=4, l=2)
+    pi, ps, st = O.query(idx, Q, 10, qProbes=30)
+    ri, rs, short = O.query_reranked(idx, Q, 10, qProbes=30, R=400, storage=storage)
+    np.testing.assert_array_equal(pi, ri)
+    np.testing.assert_array_equal(ps, rs)
