@@ -1,0 +1,244 @@
+/*
+ * fpp.h — C ABI of the MI355X (gfx950) Falconn++ hot path.
+ *
+ * Falconn++ (Pham & Liu, NeurIPS 2022) answers top-k inner-product queries on
+ * the unit sphere (Section 1, problem statement) with cross-polytope LSH
+ * tables (Section 2.2, Eq. 1) whose buckets keep only the points with the
+ * largest projections onto the bucket's random vector (Section 3.4, Algorithm 1),
+ * probed across all tables in order of |q^T r_i| (Section 3.4, multi-probing
+ * for querying).
+ *
+ * Conventions for every entry point:
+ *   - Pointers documented as "device" point to memory on the current HIP device
+ *     (for example torch.Tensor.data_ptr() of a cuda tensor); "host" pointers to
+ *     ordinary process memory. Matrices are dense row-major.
+ *   - The caller owns every buffer it passes; the library never frees or keeps
+ *     a caller pointer beyond the call (the index copies X).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream). Work is
+ *     enqueued on it; outputs are valid once the stream has reached the point
+ *     of the call. Entry points that return host data synchronise that stream.
+ *   - Return value: FPP_OK (0) or a negative FPP_E* code. On error nothing has
+ *     been written to the outputs and fpp_last_error() describes the failure.
+ *     No C++ exception crosses this boundary.
+ *   - An index is immutable after build: concurrent fpp_query calls on one index
+ *     from several threads or streams are safe.
+ *   - Inputs are assumed finite and unit-norm (Section 1); the library does not
+ *     renormalise.
+ */
+#ifndef FPP_H
+#define FPP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FPP_OK 0
+#define FPP_EINVAL (-1)    /* an argument is out of range; nothing was enqueued        */
+#define FPP_ENOMEM (-2)    /* a device or host allocation failed                        */
+#define FPP_EHIP (-3)      /* a HIP runtime call failed                                 */
+#define FPP_ECAPACITY (-4) /* a request exceeds a fixed capacity (pool, table limits)   */
+#define FPP_ESTATE (-5)    /* the object is not in a state that allows the call         */
+
+/* Scoring stores. The FP32 copy of X always exists (it gives exact scores and the rerank). */
+#define FPP_STORE_FP32 0
+#define FPP_STORE_BF16 1   /* x rounded to bfloat16, nearest-even                                */
+#define FPP_STORE_FP8 2    /* per-vector scale s = max|x|/448; codes = OCP E4M3(x/s), nearest-even */
+
+typedef struct fpp_index fpp_index;
+
+/* Build options (fpp_default_build_opts fills the defaults shown). */
+typedef struct fpp_build_opts {
+  int32_t l;              /* cross-polytope functions concatenated per table: 1 or 2 (2). Section 4
+                             uses 2, giving (2D)^2 buckets per table.                            */
+  int32_t stores;         /* bit mask of extra low-precision stores to build: 1<<FPP_STORE_BF16,
+                             1<<FPP_STORE_FP8 (0 = FP32 only)                                    */
+  int32_t keep_rounding;  /* 0: a bucket of B records keeps ceil(alpha*B/iProbes) (default);
+                             1: floor(...). alpha is taken to 6 decimals.                       */
+  int32_t tables_per_pass;/* tables hashed and sorted per pass (0 = chosen from free memory)    */
+} fpp_build_opts;
+
+void fpp_default_build_opts(fpp_build_opts* opts);
+
+/*
+ * Build an index over X (Algorithm 1 applied to each of L tables).
+ *   X       device, float32 [n][d]; copied into the index (caller may free it after return).
+ *   n       number of points, 1 <= n < 2^31.
+ *   d       dimension, 1 <= d <= 1024.
+ *   L       number of tables, 1 <= L <= 4096.
+ *   D       random vectors per cross-polytope function (2D codes), a power of two,
+ *           2 <= D <= 2048; the rotation length is P = max(D, 2^ceil(log2 d)) <= 4096.
+ *   alpha   fraction of every bucket that is kept, 0 < alpha <= 1 (Section 3.4).
+ *   iProbes buckets per point and table before filtering, 1 <= iProbes <= min(16, D^l)
+ *           (Algorithm 1, multi-probe indexing).
+ *   seed    seeds the random sign diagonals of the rotation (SplitMix64 counter stream).
+ *   out     host, receives the new index.
+ * fpp_build_index uses the default options and the default stream and returns after
+ * the build has finished. Errors: FPP_EINVAL (ranges), FPP_ENOMEM, FPP_EHIP,
+ * FPP_ECAPACITY (more than 2^32 - 1 stored ids in total).
+ */
+int fpp_build_index(const float* X, int64_t n, int32_t d, int32_t L, int32_t D, float alpha,
+                    int32_t iProbes, uint64_t seed, fpp_index** out);
+int fpp_build_index_ex(const float* X, int64_t n, int32_t d, int32_t L, int32_t D, float alpha,
+                       int32_t iProbes, uint64_t seed, const fpp_build_opts* opts, void* stream,
+                       fpp_index** out);
+
+/* Release an index and its device memory (NULL is ignored). The caller must ensure no
+ * enqueued query still uses it. */
+void fpp_free_index(fpp_index* index);
+
+/* Query options (fpp_default_query_opts fills the defaults shown). */
+typedef struct fpp_query_opts {
+  int32_t store;       /* store scored during the candidate pass: FPP_STORE_FP32 (exact scores, 0),
+                          FPP_STORE_BF16 or FPP_STORE_FP8 (approximate; requires that store)     */
+  int32_t rerank_R;    /* low-precision stores: short-list length re-scored exactly in FP32
+                          (0 = max(100, 2k)); 1 <= k <= R <= 512                                 */
+  int64_t* stats;      /* optional device int64 [m][3]: probes, probed entries (with repeats),
+                          unique candidates scored                                               */
+  double* stage_ms;    /* optional host double [4]: milliseconds spent in hashing, probe
+                          selection, gather/score/top-k and rerank, from HIP events recorded on
+                          `stream` around each kernel; when set, the call synchronises `stream`  */
+} fpp_query_opts;
+
+void fpp_default_query_opts(fpp_query_opts* opts);
+
+/*
+ * Top-k search for m queries (Section 3.4, multi-probing for querying; Section 1).
+ *   Q          device, float32 [m][d] (d of the index).
+ *   m          number of queries, m >= 0 (0 enqueues nothing).
+ *   k          results per query, 1 <= k <= 512.
+ *   qProbes    total number of (table, bucket) probes per query over all L tables, ranked by
+ *              the sum of the query's |projections| (clamped to L * D^l); >= 1.
+ *   ids_out    device, int32 [m][k]: ids by (score desc, id asc); -1 pads short results.
+ *   scores_out device, float32 [m][k]: FP32 inner products q^T x on the stored FP32 X
+ *              (after a low-precision pass, the exact FP32 rerank scores); -inf pads.
+ * Scratch memory is taken from the stream-ordered allocator on `stream`.
+ * Errors: FPP_EINVAL, FPP_ENOMEM, FPP_EHIP, FPP_ESTATE (requested store not built).
+ */
+int fpp_query(const fpp_index* index, const float* Q, int64_t m, int32_t k, int32_t qProbes,
+              int32_t* ids_out, float* scores_out, void* stream);
+int fpp_query_ex(const fpp_index* index, const float* Q, int64_t m, int32_t k, int32_t qProbes,
+                 const fpp_query_opts* opts, int32_t* ids_out, float* scores_out, void* stream);
+
+/*
+ * Mixed batch in one launch sequence: query i uses k[i] and qProbes[i] (host arrays of m
+ * entries, same ranges as above) and writes its k[i] results at ids_out + off_i and
+ * scores_out + off_i with off_i = k[0] + ... + k[i-1] (packed). Other arguments as fpp_query_ex.
+ * A query's result does not depend on the other queries of the batch.
+ */
+int fpp_query_batch(const fpp_index* index, const float* Q, int64_t m, const int32_t* k,
+                    const int32_t* qProbes, const fpp_query_opts* opts, int32_t* ids_out,
+                    float* scores_out, void* stream);
+
+/* Bytes of scratch memory fpp_query_batch needs for m queries with the given maxima. */
+int64_t fpp_query_workspace_bytes(const fpp_index* index, int64_t m, int32_t k_max,
+                                  int32_t qprobes_max, const fpp_query_opts* opts);
+
+/* Facts about a built index (host struct). */
+typedef struct fpp_index_info {
+  int64_t n;
+  int32_t d, L, D, l, P, iProbes;
+  int32_t stores;          /* bit mask of built low-precision stores               */
+  float alpha;
+  uint64_t seed;
+  int64_t buckets_per_table;
+  int64_t total_ids;       /* stored ids over all tables                            */
+  int64_t max_bucket;      /* largest kept bucket                                   */
+  int64_t device_bytes;    /* device memory held by the index                       */
+  double build_ms;         /* wall time of the build call                           */
+} fpp_index_info;
+
+int fpp_index_get_info(const fpp_index* index, fpp_index_info* info);
+/* host int64 [L]: ids stored per table. */
+int fpp_index_table_sizes(const fpp_index* index, int64_t* sizes_out);
+
+const char* fpp_last_error(void);   /* message of the last failed call on this thread */
+const char* fpp_version(void);
+
+/* ------------------------------------------------------------------------------------------
+ * Serving: a persistent request loop over one resident index (continuous batching).
+ * Requests of mixed m, k and qProbes are admitted first-in first-out while the scratch
+ * pool and a stream slot are free, packed into one launch sequence with per-query
+ * parameters, and run on `n_streams` streams so that batches overlap on the device.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct fpp_server fpp_server;
+
+typedef struct fpp_server_opts {
+  int64_t scratch_bytes;   /* scratch pool shared by in-flight batches (>= one request's need) */
+  int32_t n_streams;       /* batches in flight at once, 1..8                                   */
+  int32_t max_batch;       /* queries packed into one launch, >= 1                              */
+  int32_t store;           /* as fpp_query_opts.store                                           */
+  int32_t rerank_R;        /* as fpp_query_opts.rerank_R                                        */
+} fpp_server_opts;
+
+void fpp_default_server_opts(fpp_server_opts* opts);
+
+/* Start the loop thread. The index must outlive the server. */
+int fpp_server_create(const fpp_index* index, const fpp_server_opts* opts, fpp_server** out);
+
+/*
+ * Submit one request: Q device float32 [m][d]; ids_out / scores_out device [m][k].
+ * The buffers must stay valid until the request completes. Returns a ticket (> 0) in
+ * *ticket. Errors: FPP_EINVAL, FPP_ECAPACITY (the request alone needs more scratch than
+ * the pool holds), FPP_ESTATE (server stopping).
+ */
+int fpp_server_submit(fpp_server* server, const float* Q, int32_t m, int32_t k, int32_t qProbes,
+                      int32_t* ids_out, float* scores_out, int64_t* ticket);
+
+/* Request state: *status = 0 done, 1 pending, < 0 failed (an FPP_E* code). Times are
+ * CLOCK_MONOTONIC nanoseconds of submission and of completion (0 while pending). */
+int fpp_server_poll(fpp_server* server, int64_t ticket, int32_t* status, int64_t* t_submit_ns,
+                    int64_t* t_done_ns);
+/* Block until the request completes or timeout_ms passes (< 0: no limit). */
+int fpp_server_wait(fpp_server* server, int64_t ticket, int64_t timeout_ms, int32_t* status,
+                    int64_t* t_submit_ns, int64_t* t_done_ns);
+
+typedef struct fpp_server_stats {
+  int64_t submitted, completed, failed, batches, queries;
+  int64_t max_inflight_batches;   /* largest number of batches on the device at once */
+  int64_t scratch_high_water;     /* largest scratch in use at once (bytes)          */
+} fpp_server_stats;
+int fpp_server_get_stats(fpp_server* server, fpp_server_stats* stats);
+
+/* Stop accepting work, finish what was admitted, join the loop thread and free it. */
+void fpp_server_destroy(fpp_server* server);
+
+/* ------------------------------------------------------------------------------------------
+ * Inspection entry points (used by the parity tests; not on the query path).
+ * ------------------------------------------------------------------------------------------ */
+
+/* host int8 [L][l][3][P]: the +-1 sign diagonals of the rotation (Section 3.4). */
+int fpp_debug_signs(const fpp_index* index, int8_t* signs_out);
+
+/* Query-side hash lists: for every vector of V (device float32 [m][d]) and every (table t,
+ * function f), the D entries sorted by (|y_i| desc, i asc): abs_out device float32 and
+ * code_out device int32, both [m][L][l][D]; code = i if y_i >= 0 else i + D (Eq. 1). */
+int fpp_debug_query_lists(const fpp_index* index, const float* V, int64_t m, float* abs_out,
+                          int32_t* code_out, void* stream);
+
+/* Build-side records of table t: for every point p and r < iProbes, the bucket and key of its
+ * r-th best pair (device uint32 bucket_out / float32 key_out, [n][iProbes]). */
+int fpp_debug_build_records(const fpp_index* index, int32_t t, uint32_t* bucket_out,
+                            float* key_out, void* stream);
+
+/* CSR of table t: host uint32 offsets_out [(2D)^l + 1] (relative to the table start) and
+ * host int32 ids_out [table size]. Synchronises. */
+int fpp_debug_export_table(const fpp_index* index, int32_t t, uint32_t* offsets_out,
+                           int32_t* ids_out);
+
+/* The selected probes of each query: device int64 [m][qProbes'] with qProbes' = min(qProbes,
+ * L * D^l), each t * (2D)^l + bucket, in no particular order. */
+int fpp_debug_probes(const fpp_index* index, const float* Q, int64_t m, int32_t qProbes,
+                     int64_t* probes_out, void* stream);
+
+/* A low-precision store: store FPP_STORE_BF16 -> device uint16 [n][d]; FPP_STORE_FP8 -> device
+ * uint8 [n][d] codes plus device float32 [n] scales (scales_out ignored for BF16). */
+int fpp_debug_export_store(const fpp_index* index, int32_t store, void* codes_out,
+                           float* scales_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPP_H */

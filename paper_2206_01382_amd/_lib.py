@@ -1,0 +1,292 @@
+"""ctypes binding of libfpp (include/fpp.h): the same entry points, argument marshalling only.
+
+Tensors passed to the library must be contiguous tensors on the current HIP device; the
+library receives their data pointers and the current torch stream. Every step of the
+Falconn++ path runs in the library's HIP kernels; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfpp.so")
+
+FPP_OK = 0
+FPP_EINVAL = -1
+FPP_ENOMEM = -2
+FPP_EHIP = -3
+FPP_ECAPACITY = -4
+FPP_ESTATE = -5
+
+FPP_STORE_FP32 = 0
+FPP_STORE_BF16 = 1
+FPP_STORE_FP8 = 2
+STORES = {"fp32": FPP_STORE_FP32, "bf16": FPP_STORE_BF16, "fp8": FPP_STORE_FP8}
+
+c_i32, c_i64, c_u64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
+
+
+class fpp_build_opts(ctypes.Structure):
+    _fields_ = [("l", c_i32), ("stores", c_i32), ("keep_rounding", c_i32), ("tables_per_pass", c_i32)]
+
+
+class fpp_query_opts(ctypes.Structure):
+    _fields_ = [("store", c_i32), ("rerank_R", c_i32), ("stats", c_vp), ("stage_ms", c_vp)]
+
+
+class fpp_index_info(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("d", c_i32), ("L", c_i32), ("D", c_i32), ("l", c_i32), ("P", c_i32),
+                ("iProbes", c_i32), ("stores", c_i32), ("alpha", c_f32), ("seed", c_u64),
+                ("buckets_per_table", c_i64), ("total_ids", c_i64), ("max_bucket", c_i64),
+                ("device_bytes", c_i64), ("build_ms", ctypes.c_double)]
+
+
+class fpp_server_opts(ctypes.Structure):
+    _fields_ = [("scratch_bytes", c_i64), ("n_streams", c_i32), ("max_batch", c_i32),
+                ("store", c_i32), ("rerank_R", c_i32)]
+
+
+class fpp_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", c_i64), ("completed", c_i64), ("failed", c_i64), ("batches", c_i64),
+                ("queries", c_i64), ("max_inflight_batches", c_i64), ("scratch_high_water", c_i64)]
+
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "fpp_default_build_opts": (None, [ctypes.POINTER(fpp_build_opts)]),
+    "fpp_build_index": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_f32, c_i32, c_u64, ctypes.POINTER(c_vp)]),
+    "fpp_build_index_ex": (c_i32, [c_vp, c_i64, c_i32, c_i32, c_i32, c_f32, c_i32, c_u64,
+                                   ctypes.POINTER(fpp_build_opts), c_vp, ctypes.POINTER(c_vp)]),
+    "fpp_free_index": (None, [c_vp]),
+    "fpp_default_query_opts": (None, [ctypes.POINTER(fpp_query_opts)]),
+    "fpp_query": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
+    "fpp_query_ex": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(fpp_query_opts), c_vp, c_vp, c_vp]),
+    "fpp_query_batch": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(fpp_query_opts), c_vp, c_vp, c_vp]),
+    "fpp_query_workspace_bytes": (c_i64, [c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(fpp_query_opts)]),
+    "fpp_index_get_info": (c_i32, [c_vp, ctypes.POINTER(fpp_index_info)]),
+    "fpp_index_table_sizes": (c_i32, [c_vp, c_vp]),
+    "fpp_last_error": (ctypes.c_char_p, []),
+    "fpp_version": (ctypes.c_char_p, []),
+    "fpp_default_server_opts": (None, [ctypes.POINTER(fpp_server_opts)]),
+    "fpp_server_create": (c_i32, [c_vp, ctypes.POINTER(fpp_server_opts), ctypes.POINTER(c_vp)]),
+    "fpp_server_submit": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, ctypes.POINTER(c_i64)]),
+    "fpp_server_poll": (c_i32, [c_vp, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    "fpp_server_wait": (c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
+                                ctypes.POINTER(c_i64)]),
+    "fpp_server_get_stats": (c_i32, [c_vp, ctypes.POINTER(fpp_server_stats)]),
+    "fpp_server_destroy": (None, [c_vp]),
+    "fpp_debug_signs": (c_i32, [c_vp, c_vp]),
+    "fpp_debug_query_lists": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "fpp_debug_build_records": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "fpp_debug_export_table": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
+    "fpp_debug_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp]),
+    "fpp_debug_export_store": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+}
+
+_LIB = None
+
+
+class FppError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fpp error {code}: {msg}")
+        self.code = code
+
+
+def lib():
+    """The loaded library. Raises if libfpp.so has not been built: there is no fallback path."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2206_01382_amd.build_lib.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)   # AttributeError: the library lacks a declared entry point
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != FPP_OK:
+        raise FppError(rc, lib().fpp_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return c_vp(t.data_ptr())
+
+
+def _stream(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_vp(s.cuda_stream)
+
+
+# ------------------------------------------------------------------------------------------------
+def fpp_build_index(X, L: int, D: int, alpha: float, iProbes: int, seed: int, *, l: int = 2,
+                    stores=(), keep_rounding: int = 0, tables_per_pass: int = 0, stream=None) -> c_vp:
+    """Build an index over X (GPU float32 [n][d]); returns the opaque handle."""
+    torch = _torch()
+    xp = _dev(X, torch.float32, "X")
+    o = fpp_build_opts(l, sum(1 << STORES[s] for s in stores), keep_rounding, tables_per_pass)
+    h = c_vp()
+    _check(lib().fpp_build_index_ex(xp, X.shape[0], X.shape[1], L, D, alpha, iProbes, seed & (2 ** 64 - 1),
+                                    ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def fpp_free_index(h):
+    if h is not None and h.value:
+        lib().fpp_free_index(h)
+
+
+def fpp_query(h, Q, k: int, qProbes: int, *, store: str = "fp32", rerank_R: int = 0, stats: bool = False,
+              stream=None, out=None, stage_ms=None):
+    """Top-k of every row of Q (GPU float32 [m][d]) -> (ids int32 [m][k], scores float32 [m][k][, stats]).
+
+    ``stage_ms``: optional numpy float64 array of 4 that receives per-stage milliseconds
+    (hashing, probe selection, gather/score/top-k, rerank); the call then synchronises.
+    """
+    torch = _torch()
+    m = Q.shape[0]
+    qp = _dev(Q, torch.float32, "Q") if m else c_vp(0)
+    if out is None:
+        ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+        sc = torch.empty((m, k), dtype=torch.float32, device=Q.device)
+    else:
+        ids, sc = out
+    st = torch.empty((m, 3), dtype=torch.int64, device=Q.device) if stats else None
+    if stage_ms is not None and (stage_ms.dtype != np.float64 or stage_ms.shape != (4,)):
+        raise ValueError("stage_ms must be a float64 array of 4")
+    o = fpp_query_opts(STORES[store], rerank_R, c_vp(st.data_ptr()) if stats and m else None,
+                       stage_ms.ctypes.data_as(c_vp) if stage_ms is not None else None)
+    _check(lib().fpp_query_ex(h, qp, m, k, qProbes, ctypes.byref(o),
+                              c_vp(ids.data_ptr()) if m else c_vp(0), c_vp(sc.data_ptr()) if m else c_vp(0),
+                              _stream(stream)))
+    return (ids, sc, st) if stats else (ids, sc)
+
+
+def fpp_query_batch(h, Q, k, qProbes, *, store: str = "fp32", rerank_R: int = 0, stats: bool = False,
+                    stream=None):
+    """Mixed batch: per-query k and qProbes (sequences); results packed in query order."""
+    torch = _torch()
+    m = Q.shape[0]
+    ka = np.ascontiguousarray(np.asarray(k, dtype=np.int32))
+    pa = np.ascontiguousarray(np.asarray(qProbes, dtype=np.int32))
+    if ka.shape != (m,) or pa.shape != (m,):
+        raise ValueError("k and qProbes need one entry per query")
+    tot = int(ka.sum())
+    ids = torch.empty(tot, dtype=torch.int32, device=Q.device)
+    sc = torch.empty(tot, dtype=torch.float32, device=Q.device)
+    st = torch.empty((m, 3), dtype=torch.int64, device=Q.device) if stats else None
+    o = fpp_query_opts(STORES[store], rerank_R, c_vp(st.data_ptr()) if stats and m else None, None)
+    _check(lib().fpp_query_batch(h, _dev(Q, torch.float32, "Q") if m else c_vp(0), m,
+                                 ka.ctypes.data_as(c_vp), pa.ctypes.data_as(c_vp), ctypes.byref(o),
+                                 c_vp(ids.data_ptr()) if tot else c_vp(0),
+                                 c_vp(sc.data_ptr()) if tot else c_vp(0), _stream(stream)))
+    return (ids, sc, st) if stats else (ids, sc)
+
+
+def fpp_query_workspace_bytes(h, m: int, k_max: int, qprobes_max: int, store: str = "fp32", rerank_R: int = 0):
+    o = fpp_query_opts(STORES[store], rerank_R, None, None)
+    return int(lib().fpp_query_workspace_bytes(h, m, k_max, qprobes_max, ctypes.byref(o)))
+
+
+def fpp_index_get_info(h) -> dict:
+    inf = fpp_index_info()
+    _check(lib().fpp_index_get_info(h, ctypes.byref(inf)))
+    return {name: getattr(inf, name) for name, _ in fpp_index_info._fields_}
+
+
+def fpp_index_table_sizes(h) -> np.ndarray:
+    L = fpp_index_get_info(h)["L"]
+    out = np.zeros(L, dtype=np.int64)
+    _check(lib().fpp_index_table_sizes(h, out.ctypes.data_as(c_vp)))
+    return out
+
+
+def fpp_last_error() -> str:
+    return lib().fpp_last_error().decode()
+
+
+def fpp_version() -> str:
+    return lib().fpp_version().decode()
+
+
+# ------------------------------------------------------------------------------------------------
+def fpp_debug_signs(h) -> np.ndarray:
+    inf = fpp_index_get_info(h)
+    out = np.zeros((inf["L"], inf["l"], 3, inf["P"]), dtype=np.int8)
+    _check(lib().fpp_debug_signs(h, out.ctypes.data_as(c_vp)))
+    return out
+
+
+def fpp_debug_query_lists(h, V, stream=None):
+    torch = _torch()
+    inf = fpp_index_get_info(h)
+    m = V.shape[0]
+    a = torch.empty((m, inf["L"], inf["l"], inf["D"]), dtype=torch.float32, device=V.device)
+    c = torch.empty((m, inf["L"], inf["l"], inf["D"]), dtype=torch.int32, device=V.device)
+    _check(lib().fpp_debug_query_lists(h, _dev(V, torch.float32, "V"), m, c_vp(a.data_ptr()),
+                                       c_vp(c.data_ptr()), _stream(stream)))
+    return a, c
+
+
+def fpp_debug_build_records(h, t: int, device="cuda", stream=None):
+    torch = _torch()
+    inf = fpp_index_get_info(h)
+    b = torch.empty((inf["n"], inf["iProbes"]), dtype=torch.int32, device=device)
+    k = torch.empty((inf["n"], inf["iProbes"]), dtype=torch.float32, device=device)
+    _check(lib().fpp_debug_build_records(h, t, c_vp(b.data_ptr()), c_vp(k.data_ptr()), _stream(stream)))
+    return b, k
+
+
+def fpp_debug_export_table(h, t: int):
+    inf = fpp_index_get_info(h)
+    sizes = fpp_index_table_sizes(h)
+    off = np.zeros(inf["buckets_per_table"] + 1, dtype=np.uint32)
+    ids = np.zeros(max(int(sizes[t]), 1), dtype=np.int32)
+    _check(lib().fpp_debug_export_table(h, t, off.ctypes.data_as(c_vp), ids.ctypes.data_as(c_vp)))
+    return off.astype(np.int64), ids[: int(sizes[t])]
+
+
+def fpp_debug_probes(h, Q, qProbes: int, stream=None):
+    torch = _torch()
+    inf = fpp_index_get_info(h)
+    pairs = inf["L"] * (inf["D"] if inf["l"] == 1 else inf["D"] ** 2)
+    qc = min(qProbes, pairs)
+    out = torch.empty((Q.shape[0], qc), dtype=torch.int64, device=Q.device)
+    _check(lib().fpp_debug_probes(h, _dev(Q, torch.float32, "Q"), Q.shape[0], qProbes,
+                                  c_vp(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def fpp_debug_export_store(h, store: str, stream=None):
+    torch = _torch()
+    inf = fpp_index_get_info(h)
+    n, d = inf["n"], inf["d"]
+    if store == "bf16":
+        codes = torch.empty((n, d), dtype=torch.int16, device="cuda")
+        scales = None
+    else:
+        codes = torch.empty((n, d), dtype=torch.uint8, device="cuda")
+        scales = torch.empty(n, dtype=torch.float32, device="cuda")
+    _check(lib().fpp_debug_export_store(h, STORES[store], c_vp(codes.data_ptr()),
+                                        c_vp(scales.data_ptr()) if scales is not None else None,
+                                        _stream(stream)))
+    return codes, scales

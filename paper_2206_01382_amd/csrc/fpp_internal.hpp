@@ -1,0 +1,192 @@
+// Internal declarations shared by the HIP sources of libfpp (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fpp.h"
+
+namespace fpp {
+
+// ----------------------------------------------------------------------------------------------
+// Errors: a thread-local message plus FPP_E* codes; no exception leaves the library.
+// ----------------------------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+
+#define FPP_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t _e = (call);                                                         \
+    if (_e != hipSuccess) return ::fpp::hip_fail(_e, #call, __FILE__, __LINE__);    \
+  } while (0)
+
+#define FPP_TRY(call)                   \
+  do {                                          \
+    int _rc = (call);                            \
+    if (_rc != FPP_OK) return _rc;               \
+  } while (0)
+
+constexpr int kMaxIProbes = 16;      // build kernel keeps at most this many buckets per point
+constexpr int kMaxK = 512;           // results / short list per query
+constexpr int kMaxD = 1024;          // dimension of stored vectors
+constexpr int kMaxP = 4096;          // rotation length
+
+// ----------------------------------------------------------------------------------------------
+// The index object (opaque in the ABI).
+// ----------------------------------------------------------------------------------------------
+}  // namespace fpp
+
+struct fpp_index {
+  int64_t n = 0;
+  int32_t d = 0, L = 0, D = 0, l = 0, P = 0, iProbes = 0;
+  float alpha = 0.f;
+  int64_t alpha_micro = 0;   // alpha in millionths
+  uint64_t seed = 0;
+  int32_t keep_rounding = 0;
+  int32_t stores = 0;        // bit mask of low-precision stores
+  int64_t NB = 0;            // buckets per table, (2D)^l
+  int32_t ldx = 0;           // FP32 row stride in floats (multiple of 4)
+  int32_t ld16 = 0;          // BF16 row stride in elements (multiple of 8)
+  int32_t ld8 = 0;           // FP8 row stride in bytes (multiple of 16)
+  int device = 0;
+
+  float* X = nullptr;             // device [n][ldx]
+  uint16_t* Xbf16 = nullptr;      // device [n][ld16]
+  uint8_t* Xfp8 = nullptr;        // device [n][ld8]
+  float* fp8_scale = nullptr;     // device [n]
+  uint32_t* sign_mask = nullptr;  // device [L][l][3][P]: 0 or 0x80000000 (xor mask of the sign)
+  uint32_t* offsets = nullptr;    // device [L][NB + 1], absolute positions into ids
+  int32_t* ids = nullptr;         // device [total_ids]
+
+  std::vector<int64_t> table_base;   // host [L + 1]
+  int64_t total_ids = 0;
+  int64_t max_bucket = 0;
+  int64_t device_bytes = 0;
+  double build_ms = 0.0;
+};
+
+namespace fpp {
+
+// ----------------------------------------------------------------------------------------------
+// Host-side helpers
+// ----------------------------------------------------------------------------------------------
+std::vector<uint32_t> make_sign_masks(uint64_t seed, int L, int l, int P);
+int64_t keep_count_host(int64_t B, int64_t alpha_micro, int iProbes, int rounding);
+
+// ----------------------------------------------------------------------------------------------
+// Kernel launchers (each enqueues on `s`, returns hipError_t of the launch)
+// ----------------------------------------------------------------------------------------------
+
+// Build-side hash: records of tables [t0, t0 + Tc) for all n points.
+//   rec_bucket / rec_key: [Tc][n * K] (slot r of point p at p * K + r).
+hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_bucket,
+                             float* rec_key, hipStream_t s);
+
+// Query-side hash: sorted lists for m vectors (row stride ldv floats) and all L*l functions.
+//   la: [m][L*l][D] float32, lc: [m][L*l][D] uint16 codes.
+hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int ldv, float* la,
+                             uint16_t* lc, hipStream_t s);
+
+// Per-table build passes over a chunk of Tc tables.
+struct BuildScratch {
+  uint32_t* rec_bucket;   // [Tc][nK]
+  float* rec_key;         // [Tc][nK]
+  float* srt_key;         // [Tc][nK] records grouped by bucket
+  int32_t* srt_id;        // [Tc][nK]
+  uint32_t* cnt;          // [Tc][NB]
+  uint32_t* start;        // [Tc][NB + 1]
+  uint32_t* fill;         // [Tc][NB]
+  uint64_t* meta;         // [2 + Tc]: running base, max bucket, per-table sizes
+  uint64_t* tbase;        // [L + 1]: start of each table in the ids array
+};
+hipError_t launch_build_tables(const fpp_index* ix, int t0, int Tc, const BuildScratch& b,
+                               hipStream_t s);
+
+// Quantised stores.
+hipError_t launch_quantize(const fpp_index* ix, hipStream_t s);
+
+// Probe selection: probes [m][qcap] as absolute offset-array positions t * (NB + 1) + bucket;
+// nprobe[m] receives the count per query.
+hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc,
+                               int64_t m, const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
+                               uint32_t* probes, int32_t* nprobe, hipStream_t s);
+
+// Candidate gather, dedup, scoring and top-k (plus the FP32 rerank of a short list).
+struct ScoreArgs {
+  const float* Q;          // [m][ldq]
+  int ldq;
+  int64_t m;
+  const uint32_t* probes;  // [m][qcap]
+  const int32_t* nprobe;   // [m]
+  int32_t qcap;
+  const int32_t* k_arr;    // [m] or null -> k_uniform
+  int32_t k_uniform;
+  const int64_t* out_off;  // [m] or null -> q * k_uniform
+  int32_t store;           // FPP_STORE_*
+  int32_t rerank_R;        // short list length option (low-precision stores); 0 -> max(100, 2k)
+  int32_t* ids_out;
+  float* scores_out;
+  int32_t* short_ids;      // [m][short_ld] short lists (low-precision stores)
+  int32_t short_ld;
+  int64_t* stats;          // [m][3] or null
+  uint32_t* gbitmap;       // global dedup bitmaps (large n), [grid][ceil(n/32)] or null
+  int32_t grid;            // persistent blocks
+};
+hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s);
+hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m,
+                         const int32_t* short_ids, int short_ld, const int32_t* k_arr,
+                         int k_uniform, int R_opt, const int64_t* out_off, int32_t* ids_out,
+                         float* scores_out, hipStream_t s);
+int score_grid_blocks(const fpp_index* ix);
+int32_t short_list_len(int32_t R_opt, int32_t k);
+bool score_bitmap_in_lds(const fpp_index* ix);
+
+// ----------------------------------------------------------------------------------------------
+// Query pipeline (api.cpp), shared with the serving loop
+// ----------------------------------------------------------------------------------------------
+struct QuerySpec {
+  const float* Q = nullptr;
+  int64_t m = 0;
+  int32_t k_uniform = 0, qp_uniform = 0;
+  const int32_t* k_host = nullptr;     // per-query (host) or null
+  const int32_t* qp_host = nullptr;
+  const int32_t* k_dev = nullptr;      // per-query (device) or null
+  const int32_t* qp_dev = nullptr;
+  const int64_t* off_dev = nullptr;    // packed output offsets (device) or null
+  int32_t k_max = 0, qp_max = 0;
+  int32_t store = FPP_STORE_FP32;
+  int32_t R_opt = 0;                   // rerank short-list length (0 = max(100, 2k))
+  int32_t* ids_out = nullptr;
+  float* scores_out = nullptr;
+  int64_t* stats = nullptr;
+  double* stage_ms = nullptr;          // host [4] or null
+};
+
+struct Layout {
+  int64_t mc = 0;         // queries per chunk
+  int32_t qcap = 0;       // probes per query
+  int32_t short_ld = 0;   // short-list row length
+  bool gbm = false;       // global dedup bitmaps
+  int grid = 0;
+  size_t off_la = 0, off_lc = 0, off_probes = 0, off_np = 0, off_short = 0, off_gbm = 0, total = 0;
+};
+
+size_t a256(size_t v);
+int64_t total_pairs(const fpp_index* ix);
+int check_store(const fpp_index* ix, int32_t store);
+// Scratch layout for m queries; queries are processed in chunks so that one chunk's lists and
+// probes stay within `budget` bytes.
+Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max, int32_t store,
+                   int32_t R_opt, int64_t budget = (int64_t)1 << 30);
+// Runs hash -> probe selection -> score (-> rerank) over [0, qs.m) with device scratch `ws`
+// laid out by `ly`. Per-query arrays of qs must already be on the device.
+// `ev` (optional) receives 5 events per chunk: before hashing, after hashing, after probe
+// selection, after scoring, after the rerank.
+int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly, unsigned char* ws,
+                hipStream_t s, std::vector<hipEvent_t>* ev = nullptr);
+
+}  // namespace fpp

@@ -1,0 +1,600 @@
+// Candidate gather, dedup, scoring and top-k on gfx950 (Section 3.4 multi-probe querying;
+// Section 1 problem statement: the answer is the top-k of x^T q).
+//
+// One persistent 1024-thread workgroup per CU walks queries q = blockIdx.x, + gridDim.x, ...
+// For each query:
+//   A. the probed CSR ranges are loaded 512 at a time and prefix-summed; every thread takes one
+//      entry, reads its id and test-and-sets the id's bit in an n-bit bitmap (in LDS when n fits,
+//      else a per-workgroup bitmap in device memory). First-time ids enter an LDS queue
+//      (set semantics: an id is scored once however many buckets hold it).
+//   B. when the queue holds >= 1024 ids (and at the end) the waves score it: G lanes cover one
+//      row with 16-byte loads, each lane folds its chunks into a float32 partial in a fixed order,
+//      and a fixed xor-shuffle tree over the G lanes finishes the sum. Scores therefore do not
+//      depend on batching or on which wave computes them.
+//   C. candidates above the running k-th best key go to an LDS buffer that is bitonic-sorted and
+//      cut to the best kk whenever it fills; the final sort gives (score desc, id asc) order.
+// Keys are 64-bit: order-preserving float bits << 32 | (0xffffffff - id).
+// The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
+// scores exactly in float32 from the FP32 store.
+#include "fpp_internal.hpp"
+
+namespace fpp {
+namespace {
+
+constexpr int kBlock = 1024;
+constexpr int kWaves = kBlock / 64;
+constexpr int kQueueCap = 2048;
+constexpr int kQueueFlush = kQueueCap - kBlock;
+constexpr int kCandCap = 2048;
+constexpr int kProbeChunk = 512;
+constexpr int kLdsBitmapWords = 32768;   // 2^20 ids
+
+template <int STORE>
+struct Elems;
+template <>
+struct Elems<FPP_STORE_FP32> {
+  static constexpr int kPerChunk = 4;
+};
+template <>
+struct Elems<FPP_STORE_BF16> {
+  static constexpr int kPerChunk = 8;
+};
+template <>
+struct Elems<FPP_STORE_FP8> {
+  static constexpr int kPerChunk = 16;
+};
+
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+
+// Exact value of an OCP E4M3 code (never NaN here).
+__device__ __forceinline__ float e4m3_val(uint32_t b) {
+  const uint32_t em = b & 0x7fu;
+  const float nrm = __uint_as_float((em << 20) + (120u << 23));
+  const float sub = (float)em * 0.001953125f;   // em * 2^-9, exact
+  const float mag = em >= 8u ? nrm : sub;
+  return __uint_as_float(__float_as_uint(mag) ^ ((b & 0x80u) << 24));
+}
+
+// Fold one 16-byte chunk of a stored row into the running partial p (fixed element order).
+template <int STORE>
+__device__ __forceinline__ float fold_chunk(float p, const float* qv, uint4 w) {
+  if constexpr (STORE == FPP_STORE_FP32) {
+    p = __fmaf_rn(qv[0], __uint_as_float(w.x), p);
+    p = __fmaf_rn(qv[1], __uint_as_float(w.y), p);
+    p = __fmaf_rn(qv[2], __uint_as_float(w.z), p);
+    p = __fmaf_rn(qv[3], __uint_as_float(w.w), p);
+  } else if constexpr (STORE == FPP_STORE_BF16) {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      p = __fmaf_rn(qv[2 * i], bf16_lo(ws[i]), p);
+      p = __fmaf_rn(qv[2 * i + 1], bf16_hi(ws[i]), p);
+    }
+  } else {
+    const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) p = __fmaf_rn(qv[4 * i + b], e4m3_val((ws[i] >> (8 * b)) & 0xffu), p);
+    }
+  }
+  return p;
+}
+
+template <int G>
+__device__ __forceinline__ float tree_sum(float p) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) p += __shfl_xor(p, o, G);
+  return p;
+}
+
+// Short-list length of a query with k results (same rule as the host: R, else max(100, 2k),
+// at most kMaxK and at least k).
+__device__ __forceinline__ int short_len(int R_opt, int k) {
+  int R = R_opt > 0 ? R_opt : (2 * k > 100 ? 2 * k : 100);
+  R = R < kMaxK ? R : kMaxK;
+  return R > k ? R : k;
+}
+
+__device__ __forceinline__ uint64_t make_key(float s, int32_t id) {
+  s = s + 0.0f;   // -0 -> +0
+  const uint32_t u = __float_as_uint(s);
+  const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+  return ((uint64_t)ord << 32) | (uint32_t)(0xffffffffu - (uint32_t)id);
+}
+__device__ __forceinline__ int32_t key_id(uint64_t k) {
+  return k ? (int32_t)(0xffffffffu - (uint32_t)k) : -1;
+}
+__device__ __forceinline__ float key_score(uint64_t k) {
+  if (!k) return -INFINITY;
+  const uint32_t ord = (uint32_t)(k >> 32);
+  return __uint_as_float((ord & 0x80000000u) ? (ord & 0x7fffffffu) : ~ord);
+}
+
+// Load the query's elements matching the lane's chunks: chunk index c * G + g holds elements
+// [(c*G+g)*EPC, +EPC); elements past d are zero.
+template <int STORE, int G, int C>
+__device__ __forceinline__ void load_query(const float* qrow, int d, int g,
+                                           float (&qv)[C][Elems<STORE>::kPerChunk]) {
+  constexpr int EPC = Elems<STORE>::kPerChunk;
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int e = 0; e < EPC; ++e) {
+      const int el = (c * G + g) * EPC + e;
+      qv[c][e] = el < d ? qrow[el] : 0.0f;
+    }
+}
+
+// Block-wide bitonic sort (descending) of n = power-of-two keys in LDS.
+__device__ void block_sort_desc(uint64_t* key, int n) {
+  for (int k = 2; k <= n; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = key[i], b = key[ixj];
+          const bool desc = (i & k) == 0;
+          if (desc ? (a < b) : (a > b)) {
+            key[i] = b;
+            key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// Exclusive block scan of one u32 per thread (kBlock threads).
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t* wsum) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t t = __shfl_up(inc, o);
+    if (lane >= o) inc += t;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t r = 0;
+    for (int i = 0; i < kWaves; ++i) {
+      const uint32_t x = wsum[i];
+      wsum[i] = r;
+      r += x;
+    }
+    wsum[kWaves] = r;
+  }
+  __syncthreads();
+  const uint32_t out = wsum[w] + inc - v;
+  total = wsum[kWaves];
+  __syncthreads();
+  return out;
+}
+
+struct ScoreParams {
+  const unsigned char* Xs;   // store base
+  int64_t ld_bytes;          // store row stride in bytes
+  int nchunks;               // 16-byte chunks per stored row
+  const float* scale;        // FP8 per-row scales
+  const uint32_t* offsets;
+  const int32_t* ids;
+  int64_t n;
+  int d;
+  const float* Q;
+  int ldq;
+  int64_t m;
+  const uint32_t* probes;
+  const int32_t* nprobe;
+  int32_t qcap;
+  const int32_t* k_arr;
+  int32_t k_uniform;
+  const int64_t* out_off;
+  int32_t lowp;              // 0: FP32 store, final answer; 1: short list for the rerank
+  int32_t R_opt;             // short-list length option (0 = max(100, 2k))
+  int32_t* ids_out;
+  float* scores_out;
+  int32_t* short_ids;        // [m][short_ld]
+  int32_t short_ld;
+  int64_t* stats;
+  uint32_t* gbitmap;
+  int64_t bm_words;
+};
+
+struct SharedState {
+  uint32_t qcount;
+  uint32_t ccount;
+  uint32_t uniq;
+  uint32_t pad;
+  uint64_t thr;
+};
+
+// LDS carve-up (byte offsets).
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t kOffCand = 0;
+constexpr size_t kOffQueue = kOffCand + (size_t)kCandCap * 8;
+constexpr size_t kOffBeg = kOffQueue + (size_t)kQueueCap * 4;
+constexpr size_t kOffPre = kOffBeg + (size_t)kProbeChunk * 4;
+constexpr size_t kOffWsum = kOffPre + (size_t)(kProbeChunk + 1) * 4;
+constexpr size_t kOffState = align_up(kOffWsum + (size_t)(kWaves + 2) * 4, 8);
+constexpr size_t kOffBitmap = align_up(kOffState + sizeof(SharedState), 16);
+
+template <int STORE, int G, int C, bool LDSBM>
+__global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
+  constexpr int EPC = Elems<STORE>::kPerChunk;
+  constexpr int U = 8 / C;                 // rows in flight per lane
+  constexpr int RPI = 64 / G;              // rows per wave instruction
+  constexpr int RPW = U * RPI;             // rows per wave pass
+  constexpr int RPB = RPW * kWaves;        // rows per block pass
+  static_assert(RPB <= kCandCap / 2, "candidate buffer too small");
+
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* cand = reinterpret_cast<uint64_t*>(smem + kOffCand);
+  uint32_t* queue = reinterpret_cast<uint32_t*>(smem + kOffQueue);
+  uint32_t* s_beg = reinterpret_cast<uint32_t*>(smem + kOffBeg);
+  uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + kOffPre);
+  uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + kOffWsum);
+  SharedState* st = reinterpret_cast<SharedState*>(smem + kOffState);
+  uint32_t* bitmap = LDSBM ? reinterpret_cast<uint32_t*>(smem + kOffBitmap)
+                           : p.gbitmap + (size_t)blockIdx.x * p.bm_words;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane % G, sub = lane / G;
+  const int64_t bm_words = (p.n + 31) / 32;
+
+  if (LDSBM) {
+    for (int64_t w = tid; w < bm_words; w += kBlock) bitmap[w] = 0u;
+  }
+  __syncthreads();
+
+  for (int64_t q = blockIdx.x; q < p.m; q += gridDim.x) {
+    const int k = p.k_arr ? p.k_arr[q] : p.k_uniform;
+    const int kk = p.lowp ? short_len(p.R_opt, k) : k;   // list length kept by this pass
+    float qv[C][EPC];
+    load_query<STORE, G, C>(p.Q + q * p.ldq, p.d, g, qv);
+    if (tid == 0) {
+      st->qcount = 0;
+      st->ccount = 0;
+      st->uniq = 0;
+      st->thr = 0;
+    }
+    __syncthreads();
+
+    // ---- scoring of the queued ids
+    auto score_queue = [&]() {
+      const uint32_t rows = st->qcount;
+      for (uint32_t pb = 0; pb < rows; pb += RPB) {
+        const uint32_t base = pb + wave * RPW;
+        int32_t rid[U];
+        uint4 w[U][C];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t row = base + u * RPI + sub;
+          rid[u] = row < rows ? (int32_t)queue[row] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) {
+            const int ci = c * G + g;
+            if (rid[u] >= 0 && ci < p.nchunks)
+              w[u][c] = *reinterpret_cast<const uint4*>(p.Xs + (size_t)rid[u] * p.ld_bytes +
+                                                        (size_t)ci * 16);
+            else
+              w[u][c] = make_uint4(0u, 0u, 0u, 0u);
+          }
+        }
+        const uint64_t thr = st->thr;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          float part = 0.0f;
+#pragma unroll
+          for (int c = 0; c < C; ++c) part = fold_chunk<STORE>(part, qv[c], w[u][c]);
+          float s = tree_sum<G>(part);
+          if constexpr (STORE == FPP_STORE_FP8) {
+            if (rid[u] >= 0) s = s * p.scale[rid[u]];
+          }
+          if (g == 0 && rid[u] >= 0) {
+            const uint64_t key = make_key(s, rid[u]);
+            if (key > thr) cand[atomicAdd(&st->ccount, 1u)] = key;
+          }
+        }
+        __syncthreads();
+        if (st->ccount > (uint32_t)(kCandCap - RPB)) {
+          const uint32_t c0 = st->ccount;
+          for (int i = tid; i < kCandCap; i += kBlock)
+            if ((uint32_t)i >= c0) cand[i] = 0ull;
+          __syncthreads();
+          block_sort_desc(cand, kCandCap);
+          if (tid == 0) {
+            st->ccount = c0 < (uint32_t)kk ? c0 : (uint32_t)kk;
+            if (c0 >= (uint32_t)kk) st->thr = cand[kk - 1];
+          }
+          __syncthreads();
+        }
+      }
+      __syncthreads();
+      if (tid == 0) st->qcount = 0;
+      __syncthreads();
+    };
+
+    // ---- A: gather + dedup
+    const int32_t np = p.nprobe[q];
+    const uint32_t* pr = p.probes + (size_t)q * p.qcap;
+    uint64_t entries = 0;
+    for (int32_t pc = 0; pc < np; pc += kProbeChunk) {
+      const int npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
+      uint32_t beg = 0, len = 0;
+      if (tid < npc) {
+        const uint32_t gb = pr[pc + tid];
+        beg = p.offsets[gb];
+        len = p.offsets[gb + 1] - beg;
+      }
+      uint32_t ec;
+      const uint32_t pre = block_excl_scan(len, ec, wsum);
+      if (tid < kProbeChunk) {
+        s_beg[tid] = beg;
+        s_pre[tid] = pre;
+      }
+      if (tid == 0) s_pre[kProbeChunk] = ec;
+      __syncthreads();
+      entries += ec;
+      for (uint32_t e0 = 0; e0 < ec; e0 += kBlock) {
+        const uint32_t e = e0 + tid;
+        int32_t nid = -1;
+        if (e < ec) {
+          int lo = 0, hi = npc;   // s_pre[lo] <= e < s_pre[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= e) lo = mid;
+            else hi = mid;
+          }
+          const int32_t id = p.ids[s_beg[lo] + (e - s_pre[lo])];
+          const uint32_t bit = 1u << (id & 31);
+          const uint32_t old = atomicOr(&bitmap[id >> 5], bit);
+          if (!(old & bit)) nid = id;
+        }
+        const uint64_t mask = __ballot(nid >= 0);
+        const uint32_t cnt = (uint32_t)__popcll(mask);
+        if (cnt) {
+          uint32_t basepos = 0;
+          if (lane == 0) {
+            basepos = atomicAdd(&st->qcount, cnt);
+            atomicAdd(&st->uniq, cnt);
+          }
+          basepos = __shfl(basepos, 0);
+          if (nid >= 0) {
+            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            queue[basepos + rank] = (uint32_t)nid;
+          }
+        }
+        __syncthreads();
+        if (st->qcount >= (uint32_t)kQueueFlush) score_queue();
+      }
+      __syncthreads();
+    }
+    if (st->qcount) score_queue();
+
+    // ---- C: final order and output
+    {
+      const uint32_t c0 = st->ccount;
+      for (int i = tid; i < kCandCap; i += kBlock)
+        if ((uint32_t)i >= c0) cand[i] = 0ull;
+      __syncthreads();
+      block_sort_desc(cand, kCandCap);
+      if (!p.lowp) {
+        const int64_t o = p.out_off ? p.out_off[q] : q * (int64_t)k;
+        for (int r = tid; r < k; r += kBlock) {
+          const uint64_t key = (uint32_t)r < c0 ? cand[r] : 0ull;
+          p.ids_out[o + r] = key_id(key);
+          p.scores_out[o + r] = key_score(key);
+        }
+      } else {
+        int32_t* so = p.short_ids + (size_t)q * p.short_ld;
+        for (int r = tid; r < kk; r += kBlock) {
+          const uint64_t key = (uint32_t)r < c0 ? cand[r] : 0ull;
+          so[r] = key_id(key);
+        }
+      }
+      if (tid == 0 && p.stats) {
+        p.stats[q * 3 + 0] = np;
+        p.stats[q * 3 + 1] = (int64_t)entries;
+        p.stats[q * 3 + 2] = st->uniq;
+      }
+    }
+
+    // ---- clear the dedup bitmap
+    if (LDSBM) {
+      for (int64_t w = tid; w < bm_words; w += kBlock) bitmap[w] = 0u;
+    } else {
+      for (int32_t pc = 0; pc < np; pc += kProbeChunk) {
+        const int npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
+        for (int i = wave; i < npc; i += kWaves) {
+          const uint32_t gb = pr[pc + i];
+          const uint32_t b0 = p.offsets[gb], b1 = p.offsets[gb + 1];
+          for (uint32_t e = b0 + lane; e < b1; e += 64) bitmap[p.ids[e] >> 5] = 0u;
+        }
+      }
+      __threadfence_block();
+    }
+    __syncthreads();
+  }
+}
+
+// Exact float32 rerank of a short list (one 256-thread block per query); the same lane layout
+// and reduction tree as the FP32 scoring pass, so a reranked score equals the FP32-path score.
+template <int G, int C>
+__global__ __launch_bounds__(256) void rerank_kernel(
+    const float* __restrict__ X, int64_t ldx, int nchunks, int d, const float* __restrict__ Q,
+    int ldq, int64_t m, const int32_t* __restrict__ short_ids, int short_ld,
+    const int32_t* __restrict__ k_arr, int k_uniform, int R_opt, const int64_t* __restrict__ out_off,
+    int32_t* __restrict__ ids_out, float* __restrict__ scores_out) {
+  constexpr int RPI = 64 / G;
+  __shared__ uint64_t key[kMaxK];
+  const int64_t q = blockIdx.x;
+  if (q >= m) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane % G, sub = lane / G;
+  const int k = k_arr ? k_arr[q] : k_uniform;
+  const int R = short_len(R_opt, k);
+  float qv[C][4];
+  load_query<FPP_STORE_FP32, G, C>(Q + q * ldq, d, g, qv);
+  const int32_t* sl = short_ids + (size_t)q * short_ld;
+  int Rp2 = 1;
+  while (Rp2 < R) Rp2 <<= 1;
+  for (int r0 = 0; r0 < Rp2; r0 += 4 * RPI) {
+    const int r = r0 + wave * RPI + sub;
+    const int32_t id = r < R ? sl[r] : -1;
+    float part = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      const int ci = c * G + g;
+      uint4 w = make_uint4(0u, 0u, 0u, 0u);
+      if (id >= 0 && ci < nchunks)
+        w = *reinterpret_cast<const uint4*>(X + (size_t)id * ldx + (size_t)ci * 4);
+      part = fold_chunk<FPP_STORE_FP32>(part, qv[c], w);
+    }
+    const float s = tree_sum<G>(part);
+    if (g == 0 && r < Rp2) key[r] = id >= 0 ? make_key(s, id) : 0ull;
+  }
+  __syncthreads();
+  block_sort_desc(key, Rp2);
+  const int64_t o = out_off ? out_off[q] : q * (int64_t)k;
+  for (int r = tid; r < k; r += 256) {
+    const uint64_t kk = r < Rp2 ? key[r] : 0ull;
+    ids_out[o + r] = key_id(kk);
+    scores_out[o + r] = key_score(kk);
+  }
+}
+
+size_t score_lds_bytes(bool ldsbm) {
+  return kOffBitmap + (ldsbm ? (size_t)kLdsBitmapWords * 4 : 0);
+}
+
+template <int STORE, int G, int C>
+hipError_t launch_score_t(const ScoreParams& sp, int grid, bool ldsbm, hipStream_t s) {
+  const size_t lds = score_lds_bytes(ldsbm);
+  if (ldsbm) {
+    auto kern = score_kernel<STORE, G, C, true>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, sp);
+  } else {
+    auto kern = score_kernel<STORE, G, C, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, sp);
+  }
+  return hipGetLastError();
+}
+
+// (G, C) per store and chunk count: G = lanes per row (power of two), C = chunks per lane.
+template <int STORE>
+hipError_t dispatch_store(const ScoreParams& sp, int grid, bool ldsbm, hipStream_t s) {
+  const int nc = sp.nchunks;
+  if (nc <= 8) return launch_score_t<STORE, 8, 1>(sp, grid, ldsbm, s);
+  if (nc <= 16) return launch_score_t<STORE, 16, 1>(sp, grid, ldsbm, s);
+  if (nc <= 32) return launch_score_t<STORE, 32, 1>(sp, grid, ldsbm, s);
+  if (nc <= 64) return launch_score_t<STORE, 64, 1>(sp, grid, ldsbm, s);
+  if (nc <= 128) return launch_score_t<STORE, 64, 2>(sp, grid, ldsbm, s);
+  if (nc <= 256) return launch_score_t<STORE, 64, 4>(sp, grid, ldsbm, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+bool score_bitmap_in_lds(const fpp_index* ix) {
+  if (ix->n > (int64_t)kLdsBitmapWords * 32) return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  int lds_max = 0;
+  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return false;
+  return (size_t)lds_max >= score_lds_bytes(true);
+}
+
+int score_grid_blocks(const fpp_index* ix) {
+  (void)ix;
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) {
+  if (a.m <= 0) return hipSuccess;
+  ScoreParams sp{};
+  sp.offsets = ix->offsets;
+  sp.ids = ix->ids;
+  sp.n = ix->n;
+  sp.d = ix->d;
+  sp.Q = a.Q;
+  sp.ldq = a.ldq;
+  sp.m = a.m;
+  sp.probes = a.probes;
+  sp.nprobe = a.nprobe;
+  sp.qcap = a.qcap;
+  sp.k_arr = a.k_arr;
+  sp.k_uniform = a.k_uniform;
+  sp.out_off = a.out_off;
+  sp.ids_out = a.ids_out;
+  sp.scores_out = a.scores_out;
+  sp.stats = a.stats;
+  sp.gbitmap = a.gbitmap;
+  sp.bm_words = (ix->n + 31) / 32;
+  sp.short_ids = a.short_ids;
+  sp.short_ld = a.short_ld;
+  sp.lowp = a.store == FPP_STORE_FP32 ? 0 : 1;
+  sp.R_opt = a.rerank_R;
+  const bool ldsbm = score_bitmap_in_lds(ix);
+  if (!ldsbm && !a.gbitmap) return hipErrorInvalidValue;
+  const int grid = a.grid;
+  switch (a.store) {
+    case FPP_STORE_FP32:
+      sp.Xs = reinterpret_cast<const unsigned char*>(ix->X);
+      sp.ld_bytes = (int64_t)ix->ldx * 4;
+      sp.nchunks = ix->ldx / 4;
+      return dispatch_store<FPP_STORE_FP32>(sp, grid, ldsbm, s);
+    case FPP_STORE_BF16:
+      sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xbf16);
+      sp.ld_bytes = (int64_t)ix->ld16 * 2;
+      sp.nchunks = ix->ld16 / 8;
+      return dispatch_store<FPP_STORE_BF16>(sp, grid, ldsbm, s);
+    case FPP_STORE_FP8:
+      sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xfp8);
+      sp.ld_bytes = (int64_t)ix->ld8;
+      sp.nchunks = ix->ld8 / 16;
+      sp.scale = ix->fp8_scale;
+      return dispatch_store<FPP_STORE_FP8>(sp, grid, ldsbm, s);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m,
+                         const int32_t* short_ids, int short_ld, const int32_t* k_arr,
+                         int k_uniform, int R_opt, const int64_t* out_off, int32_t* ids_out,
+                         float* scores_out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int nc = ix->ldx / 4;
+#define FPP_RERANK(GG, CC)                                                                      \
+  hipLaunchKernelGGL((rerank_kernel<GG, CC>), dim3((unsigned)m), dim3(256), 0, s, ix->X,       \
+                     (int64_t)ix->ldx, nc, ix->d, Q, ldq, m, short_ids, short_ld, k_arr,        \
+                     k_uniform, R_opt, out_off, ids_out, scores_out)
+  if (nc <= 8) FPP_RERANK(8, 1);
+  else if (nc <= 16) FPP_RERANK(16, 1);
+  else if (nc <= 32) FPP_RERANK(32, 1);
+  else if (nc <= 64) FPP_RERANK(64, 1);
+  else if (nc <= 128) FPP_RERANK(64, 2);
+  else if (nc <= 256) FPP_RERANK(64, 4);
+  else return hipErrorInvalidValue;
+#undef FPP_RERANK
+  return hipGetLastError();
+}
+
+}  // namespace fpp

@@ -1,0 +1,425 @@
+"""GPU path (C ABI) against the CPU oracle, element by element, on seeded synthetic inputs.
+
+Bar: hash lists, build records, CSR tables, probe sets and candidate counts are bit-exact;
+top-k ids are identical except where two candidates' float64 scores lie within the float32
+reduction bound (adjudicated near-ties, counted); float32 scores are within 1e-6 relative of
+the oracle's float64 dot products, or within the float32 reduction bound where that is looser.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synthdata
+from oracle import falconn as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2206_01382_amd as F
+    F.lib()
+    yield
+
+
+def F():
+    import paper_2206_01382_amd as F
+    return F
+
+
+# ----------------------------------------------------------------------------------------------
+# configurations: (name, data kind, n, d, L, D, l, alpha, iProbes, m)
+CONFIGS = {
+    "c1_gauss_10k_d64": dict(kind="c1"),
+    "l2_clustered": dict(kind="cl", n=20_000, d=128, L=6, D=32, l=2, alpha=0.3, iProbes=3, m=40,
+                         centers=50, spread=0.3),
+    "pad_d100_D16": dict(kind="cl", n=4_000, d=100, L=5, D=16, l=2, alpha=0.5, iProbes=2, m=30,
+                         centers=20, spread=0.4),
+    "wideD_d20_D64": dict(kind="cl", n=3_000, d=20, L=3, D=64, l=2, alpha=0.25, iProbes=4, m=30,
+                          centers=10, spread=0.5),
+    "p256_lanes2": dict(kind="cl", n=3_000, d=200, L=2, D=128, l=2, alpha=0.3, iProbes=3, m=20,
+                        centers=10, spread=0.4),
+    "p512_d300_D256": dict(kind="cl", n=2_000, d=300, L=2, D=256, l=2, alpha=0.2, iProbes=3, m=20,
+                           centers=10, spread=0.4),
+    "k16_iprobes10": dict(kind="cl", n=2_000, d=64, L=3, D=32, l=2, alpha=0.4, iProbes=10, m=20,
+                          centers=10, spread=0.4),
+    "l1_D8_iprobes3": dict(kind="cl", n=1_500, d=12, L=4, D=8, l=1, alpha=0.6, iProbes=3, m=20,
+                           centers=5, spread=0.5),
+}
+SEED = 1234
+
+
+def make(name):
+    c = CONFIGS[name]
+    if c["kind"] == "c1":
+        w = synthdata.workload("c1_gauss_10k_d64")
+        return dict(X=w.X, Q=w.Q, L=w.L, D=w.D, l=w.l, alpha=w.alpha, iProbes=w.iProbes)
+    X, Q = synthdata.clustered_sphere(c["n"], c["d"], c["m"], c["centers"], c["spread"], seed=7)
+    return dict(X=X, Q=Q, L=c["L"], D=c["D"], l=c["l"], alpha=c["alpha"], iProbes=c["iProbes"])
+
+
+_cache = {}
+
+
+def built(name):
+    """(workload dict, oracle index, GPU handle, X on device, Q on device) — built once."""
+    if name not in _cache:
+        w = make(name)
+        oi = O.build_index(w["X"], w["L"], w["D"], w["alpha"], w["iProbes"], SEED, l=w["l"])
+        Xd = torch.from_numpy(w["X"]).cuda()
+        Qd = torch.from_numpy(w["Q"]).cuda()
+        h = F().fpp_build_index(Xd, w["L"], w["D"], w["alpha"], w["iProbes"], SEED, l=w["l"],
+                                stores=("bf16", "fp8"))
+        torch.cuda.synchronize()
+        _cache[name] = (w, oi, h, Xd, Qd)
+    return _cache[name]
+
+
+def lane_layout(d):
+    nc = (d + 3) // 4
+    for G in (8, 16, 32, 64):
+        if nc <= G:
+            return G, 1
+    return 64, (2 if nc <= 128 else 4)
+
+
+def score_tol(s64, sabs, d):
+    G, C = lane_layout(d)
+    gam = (4 * C + math.log2(G) + 1) * 2.0 ** -24
+    return np.maximum(1e-6 * np.abs(s64), gam * sabs)
+
+
+def check_topk(X, Q, gi, gs, oi_ids, oi_sc, k, d):
+    """ids equal up to adjudicated near-ties; scores within tolerance. Returns #swaps."""
+    gi = gi.astype(np.int64)
+    swaps = 0
+    X64 = X.astype(np.float64)
+    for r in range(Q.shape[0]):
+        q = Q[r].astype(np.float64)
+        valid = gi[r] >= 0
+        assert np.array_equal(valid, oi_ids[r] >= 0), (r, gi[r], oi_ids[r])
+        ids = gi[r][valid]
+        assert len(set(ids.tolist())) == len(ids)
+        s64 = X64[ids] @ q
+        sabs = np.abs(X64[ids] * q).sum(1)
+        tol = score_tol(s64, sabs, d)
+        assert np.all(np.abs(gs[r][valid].astype(np.float64) - s64) <= tol), r
+        assert np.all(np.isneginf(gs[r][~valid]))
+        if not np.array_equal(gi[r], oi_ids[r]):
+            # the r-th best value must agree within the float32 bound
+            assert np.all(np.abs(s64 - oi_sc[r][valid]) <= 2 * tol + 1e-300), (r, gi[r], oi_ids[r])
+            swaps += int(np.sum(gi[r] != oi_ids[r]))
+    return swaps
+
+
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_signs_match(name):
+    w, oi, h, Xd, Qd = built(name)
+    np.testing.assert_array_equal(F().fpp_debug_signs(h), oi.signs)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_query_hash_lists_bit_exact(name):
+    w, oi, h, Xd, Qd = built(name)
+    V = np.concatenate([w["Q"], w["X"][:50]])
+    a, c = F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda())
+    a, c = a.cpu().numpy(), c.cpu().numpy()
+    for t in range(w["L"]):
+        for f in range(w["l"]):
+            hl = O.hash_lists(V, oi.signs[t, f], w["D"])
+            np.testing.assert_array_equal(a[:, t, f].view(np.uint32), hl.a.view(np.uint32))
+            np.testing.assert_array_equal(c[:, t, f], hl.code)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_build_records_bit_exact(name):
+    w, oi, h, Xd, Qd = built(name)
+    for t in sorted({0, w["L"] - 1}):
+        b, k = F().fpp_debug_build_records(h, t)
+        torch.cuda.synchronize()
+        lists = [O.hash_lists(w["X"], oi.signs[t, f], w["D"]) for f in range(w["l"])]
+        ob, ok = O.top_pairs(lists, w["D"], w["iProbes"])
+        np.testing.assert_array_equal(b.cpu().numpy().astype(np.int64), ob)
+        np.testing.assert_array_equal(k.cpu().numpy().view(np.uint32), ok.view(np.uint32))
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_tables_bit_exact(name):
+    w, oi, h, Xd, Qd = built(name)
+    sizes = F().fpp_index_table_sizes(h)
+    for t in range(w["L"]):
+        off, ids = F().fpp_debug_export_table(h, t)
+        np.testing.assert_array_equal(off, oi.offsets[t])
+        np.testing.assert_array_equal(ids, oi.ids[t])
+        assert sizes[t] == len(oi.ids[t])
+    info = F().fpp_index_get_info(h)
+    assert info["total_ids"] == sum(len(i) for i in oi.ids)
+    assert info["max_bucket"] == max(int(np.max(np.diff(o))) for o in oi.offsets)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+def test_probe_sets_bit_exact(name):
+    w, oi, h, Xd, Qd = built(name)
+    total = w["L"] * (w["D"] ** w["l"])
+    for qp in sorted({1, 17, 4 * w["L"], 50 * w["L"], total, total + 5}):
+        g = F().fpp_debug_probes(h, Qd, qp).cpu().numpy()
+        for r in range(w["Q"].shape[0]):
+            ref = O.probes(oi, w["Q"][r], qp)
+            assert sorted(g[r].tolist()) == sorted(ref.tolist()), (qp, r)
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("k", [1, 10, 100])
+def test_query_fp32_matches_oracle(name, k):
+    w, oi, h, Xd, Qd = built(name)
+    qp = 8 * w["L"]
+    ids, sc, st = F().fpp_query(h, Qd, k, qp, stats=True)
+    oids, osc, ost = O.query(oi, w["Q"], k, qp)
+    np.testing.assert_array_equal(st.cpu().numpy(), ost)
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, k, w["X"].shape[1])
+    assert swaps <= max(2, w["Q"].shape[0] * k // 200), swaps
+
+
+def test_query_c1_published_qprobes():
+    """The small workload as specified: k = 10, 4 probes per table (40 in total), and the
+    literal total of 4."""
+    w, oi, h, Xd, Qd = built("c1_gauss_10k_d64")
+    for qp in (40, 4):
+        ids, sc = F().fpp_query(h, Qd, 10, qp)
+        oids, osc, _ = O.query(oi, w["Q"], 10, qp)
+        assert check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 64) <= 2
+
+
+# ----------------------------------------------------------------------------------------------
+def test_mixed_batch_equals_single_queries():
+    w, oi, h, Xd, Qd = built("l2_clustered")
+    m = Qd.shape[0]
+    rng = np.random.default_rng(0)
+    ks = rng.choice([1, 10, 100], size=m)
+    qps = rng.choice([20, 50, 200], size=m) * w["L"] // 4
+    bi, bs = F().fpp_query_batch(h, Qd, ks, qps)
+    bi, bs = bi.cpu().numpy(), bs.cpu().numpy()
+    off = 0
+    for r in range(m):
+        si, ss = F().fpp_query(h, Qd[r:r + 1].contiguous(), int(ks[r]), int(qps[r]))
+        np.testing.assert_array_equal(bi[off:off + ks[r]], si.cpu().numpy()[0])
+        np.testing.assert_array_equal(bs[off:off + ks[r]].view(np.uint32), ss.cpu().numpy()[0].view(np.uint32))
+        off += ks[r]
+
+
+def test_determinism_rebuild_and_requery():
+    w, oi, h, Xd, Qd = built("l2_clustered")
+    h2 = F().fpp_build_index(Xd, w["L"], w["D"], w["alpha"], w["iProbes"], SEED, l=w["l"], tables_per_pass=1)
+    try:
+        for t in range(w["L"]):
+            a = F().fpp_debug_export_table(h, t)
+            b = F().fpp_debug_export_table(h2, t)
+            np.testing.assert_array_equal(a[0], b[0])
+            np.testing.assert_array_equal(a[1], b[1])
+        r1 = F().fpp_query(h, Qd, 10, 100)
+        r2 = F().fpp_query(h2, Qd, 10, 100)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            r3 = F().fpp_query(h, Qd, 10, 100)
+        s.synchronize()
+        for r in (r2, r3):
+            assert torch.equal(r1[0], r[0]) and torch.equal(r1[1], r[1])
+    finally:
+        F().fpp_free_index(h2)
+
+
+def test_chunked_queries_equal_one_chunk():
+    """Many queries (more than one persistent pass per block) give the per-query results."""
+    w, oi, h, Xd, Qd = built("wideD_d20_D64")
+    Qbig = Qd.repeat(40, 1).contiguous()
+    ids, sc = F().fpp_query(h, Qbig, 10, 30)
+    ref_i, ref_s = F().fpp_query(h, Qd, 10, 30)
+    m = Qd.shape[0]
+    for rep in range(40):
+        assert torch.equal(ids[rep * m:(rep + 1) * m], ref_i)
+        assert torch.equal(sc[rep * m:(rep + 1) * m], ref_s)
+
+
+# ----------------------------------------------------------------------------------------------
+# edge cases
+def _small_index(X, L, D, alpha, iProbes, l, seed=3):
+    Xd = torch.from_numpy(np.ascontiguousarray(X, dtype=np.float32)).cuda()
+    return Xd, F().fpp_build_index(Xd, L, D, alpha, iProbes, seed, l=l)
+
+
+def test_padding_when_fewer_candidates_than_k():
+    X, Q = synthdata.clustered_sphere(500, 16, 5, 5, 0.4, seed=1)
+    Xd, h = _small_index(X, 2, 8, 0.2, 1, 2)
+    try:
+        oi = O.build_index(X, 2, 8, 0.2, 1, 3, l=2)
+        Qd = torch.from_numpy(Q).cuda()
+        ids, sc = F().fpp_query(h, Qd, 512, 1)
+        oids, osc, _ = O.query(oi, Q, 512, 1)
+        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 512, 16)
+        assert (ids.cpu().numpy() == -1).any()
+    finally:
+        F().fpp_free_index(h)
+
+
+def test_n_smaller_than_k_and_full_probing():
+    X, Q = synthdata.clustered_sphere(5, 8, 3, 2, 0.5, seed=2)
+    Xd, h = _small_index(X, 3, 4, 1.0, 1, 2)
+    try:
+        oi = O.build_index(X, 3, 4, 1.0, 1, 3, l=2)
+        Qd = torch.from_numpy(Q).cuda()
+        ids, sc = F().fpp_query(h, Qd, 10, 10 ** 6)
+        oids, osc, _ = O.query(oi, Q, 10, 10 ** 6)
+        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 8)
+    finally:
+        F().fpp_free_index(h)
+
+
+def test_duplicate_points_and_zero_query():
+    X, Q = synthdata.clustered_sphere(800, 32, 6, 4, 0.3, seed=3)
+    X[10] = X[5]
+    X[11] = X[5]
+    Q[0] = X[5]
+    Q[1] = 0.0
+    Xd, h = _small_index(X, 4, 16, 0.5, 2, 2)
+    try:
+        oi = O.build_index(X, 4, 16, 0.5, 2, 3, l=2)
+        for t in range(4):
+            off, ids = F().fpp_debug_export_table(h, t)
+            np.testing.assert_array_equal(ids, oi.ids[t])
+        Qd = torch.from_numpy(Q).cuda()
+        ids, sc = F().fpp_query(h, Qd, 10, 64)
+        oids, osc, _ = O.query(oi, Q, 10, 64)
+        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 32)
+        got = ids.cpu().numpy()[0][:3].tolist()
+        assert got == [5, 10, 11] or oids[0][:3].tolist() != [5, 10, 11]
+        np.testing.assert_array_equal(ids.cpu().numpy()[0], oids[0])
+    finally:
+        F().fpp_free_index(h)
+
+
+def test_tiny_d1_D2_L1():
+    X = np.where(np.arange(50) % 2 == 0, 1.0, -1.0).astype(np.float32)[:, None]
+    Q = np.array([[1.0], [-1.0]], np.float32)
+    Xd, h = _small_index(X, 1, 2, 1.0, 1, 1)
+    try:
+        oi = O.build_index(X, 1, 2, 1.0, 1, 3, l=1)
+        off, ids = F().fpp_debug_export_table(h, 0)
+        np.testing.assert_array_equal(off, oi.offsets[0])
+        np.testing.assert_array_equal(ids, oi.ids[0])
+        Qd = torch.from_numpy(Q).cuda()
+        gi, gs = F().fpp_query(h, Qd, 5, 2)
+        oids, osc, _ = O.query(oi, Q, 5, 2)
+        np.testing.assert_array_equal(gi.cpu().numpy(), oids)
+    finally:
+        F().fpp_free_index(h)
+
+
+def test_empty_query_batch_and_errors():
+    w, oi, h, Xd, Qd = built("l2_clustered")
+    ids, sc = F().fpp_query(h, Qd[:0], 10, 10)
+    assert ids.shape == (0, 10)
+    with pytest.raises(F().FppError):
+        F().fpp_query(h, Qd, 0, 10)
+    with pytest.raises(F().FppError):
+        F().fpp_query(h, Qd, 600, 10)
+    with pytest.raises(F().FppError):
+        F().fpp_query(h, Qd, 10, 0)
+    h1 = F().fpp_build_index(Xd, 2, 16, 0.5, 1, 5)
+    try:
+        with pytest.raises(F().FppError) as e:
+            F().fpp_query(h1, Qd, 10, 10, store="bf16")
+        assert e.value.code == F().FPP_ESTATE
+    finally:
+        F().fpp_free_index(h1)
+
+
+# ----------------------------------------------------------------------------------------------
+# precision stores
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64"])
+def test_stores_bit_exact(name):
+    w, oi, h, Xd, Qd = built(name)
+    b, _ = F().fpp_debug_export_store(h, "bf16")
+    np.testing.assert_array_equal(b.cpu().numpy().view(np.uint16), O.bf16_bits(w["X"]))
+    c, s = F().fpp_debug_export_store(h, "fp8")
+    oc, os_ = O.quantize_fp8_rows(w["X"])
+    np.testing.assert_array_equal(s.cpu().numpy().view(np.uint32), os_.view(np.uint32))
+    np.testing.assert_array_equal(c.cpu().numpy(), oc)
+
+
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256"])
+@pytest.mark.parametrize("store", ["bf16", "fp8"])
+def test_query_low_precision_with_rerank(name, store):
+    w, oi, h, Xd, Qd = built(name)
+    k, qp = 10, 8 * w["L"]
+    ids, sc = F().fpp_query(h, Qd, k, qp, store=store)
+    oids, osc, _ = O.query_reranked(oi, w["Q"], k, qp, R=100, storage=store)
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, k, w["X"].shape[1])
+    assert swaps <= max(3, w["Q"].shape[0] * k // 50), swaps
+    # rerank scores equal the exact FP32 path's scores for the same ids
+    fi, fs = F().fpp_query(h, Qd, k, qp)
+    same = (ids == fi).all(dim=1)
+    assert torch.equal(sc[same], fs[same])
+
+
+def test_fp8_decode_and_low_precision_score_error():
+    """Approximate scores of the low-precision stores against float64 on the dequantised store."""
+    w, oi, h, Xd, Qd = built("l2_clustered")
+    for store in ("bf16", "fp8"):
+        deq = O.dequantized_store(w["X"], store)
+        ids, sc = F().fpp_query(h, Qd, 100, 8 * w["L"], store=store, rerank_R=100)
+        # with R = k the rerank is a pure reorder of the short list: scores are exact FP32
+        gi = ids.cpu().numpy().astype(np.int64)
+        for r in range(gi.shape[0]):
+            v = gi[r][gi[r] >= 0]
+            s64 = w["X"][v].astype(np.float64) @ w["Q"][r].astype(np.float64)
+            assert np.all(np.abs(sc.cpu().numpy()[r][: len(v)] - s64) <= 1e-6 * np.abs(s64) + 1e-6)
+        del deq
+
+
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.timeout(600)
+def test_full_size_c2_sampled():
+    """n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3, in the launch
+    configuration of the benchmark: sampled tables bit-exact, sampled queries' probes bit-exact,
+    and their top-k equal to exact search over the candidates those probes select."""
+    w = synthdata.workload("c2_cluster_1m_d128", m=2000)
+    Xd = torch.from_numpy(w.X).cuda()
+    h = F().fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l)
+    try:
+        S = O.rotation_signs(42, w.L, w.l, 128)
+        np.testing.assert_array_equal(F().fpp_debug_signs(h), S)
+        for t in (0, w.L - 1):
+            off, ids = F().fpp_debug_export_table(h, t)
+            ooff, oids, _ = O.build_table(w.X, S[t], w.D, w.l, w.alpha, w.iProbes)
+            np.testing.assert_array_equal(off, ooff)
+            np.testing.assert_array_equal(ids, oids)
+        Qd = torch.from_numpy(w.Q).cuda()
+        qp = 50 * w.L
+        gi, gs, st = F().fpp_query(h, Qd, 10, qp, stats=True)
+        gi, gs, st = gi.cpu().numpy(), gs.cpu().numpy(), st.cpu().numpy()
+        tables = {}
+        shell = O.Index(X=w.X, L=w.L, D=w.D, l=w.l, P=128, alpha=w.alpha, iProbes=w.iProbes, seed=42, signs=S)
+        NB = O.n_buckets(w.D, w.l)
+        for r in (0, 1, 2, 1999):
+            pr = O.probes(shell, w.Q[r], qp)
+            gp = F().fpp_debug_probes(h, Qd[r:r + 1].contiguous(), qp).cpu().numpy()[0]
+            assert sorted(gp.tolist()) == sorted(pr.tolist())
+            cand = []
+            for p in pr:
+                t, b = divmod(int(p), NB)
+                if t not in tables:
+                    tables[t] = F().fpp_debug_export_table(h, t)
+                off, ids = tables[t]
+                cand.append(ids[off[b]:off[b + 1]])
+            cand = np.unique(np.concatenate(cand).astype(np.int64))
+            assert st[r, 2] == len(cand)
+            s64 = O.scores_f64(w.X, w.Q[r], cand)
+            ri, rs = O.topk_order(s64, cand, 10)
+            check_topk(w.X, w.Q[r:r + 1], gi[r:r + 1], gs[r:r + 1], ri[None], rs[None], 10, 128)
+    finally:
+        F().fpp_free_index(h)
