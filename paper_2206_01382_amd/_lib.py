@@ -290,3 +290,44 @@ def fpp_debug_export_store(h, store: str, stream=None):
                                         c_vp(scales.data_ptr()) if scales is not None else None,
                                         _stream(stream)))
     return codes, scales
+
+
+# ------------------------------------------------------------------------------------------------
+# serving
+def fpp_server_create(h, *, scratch_bytes: int = 2 << 30, n_streams: int = 2, max_batch: int = 1024,
+                      store: str = "fp32", rerank_R: int = 0) -> c_vp:
+    o = fpp_server_opts(scratch_bytes, n_streams, max_batch, STORES[store], rerank_R)
+    sv = c_vp()
+    _check(lib().fpp_server_create(h, ctypes.byref(o), ctypes.byref(sv)))
+    return sv
+
+
+def fpp_server_submit(sv, q_ptr: int, m: int, k: int, qProbes: int, ids_ptr: int, scores_ptr: int) -> int:
+    """Submit m queries at device address q_ptr; results go to ids_ptr / scores_ptr ([m][k])."""
+    t = c_i64()
+    _check(lib().fpp_server_submit(sv, c_vp(q_ptr), m, k, qProbes, c_vp(ids_ptr), c_vp(scores_ptr),
+                                   ctypes.byref(t)))
+    return t.value
+
+
+def fpp_server_poll(sv, ticket: int):
+    st, ts, td = c_i32(), c_i64(), c_i64()
+    _check(lib().fpp_server_poll(sv, ticket, ctypes.byref(st), ctypes.byref(ts), ctypes.byref(td)))
+    return st.value, ts.value, td.value
+
+
+def fpp_server_wait(sv, ticket: int, timeout_ms: int = -1):
+    st, ts, td = c_i32(), c_i64(), c_i64()
+    _check(lib().fpp_server_wait(sv, ticket, timeout_ms, ctypes.byref(st), ctypes.byref(ts), ctypes.byref(td)))
+    return st.value, ts.value, td.value
+
+
+def fpp_server_get_stats(sv) -> dict:
+    s = fpp_server_stats()
+    _check(lib().fpp_server_get_stats(sv, ctypes.byref(s)))
+    return {name: getattr(s, name) for name, _ in fpp_server_stats._fields_}
+
+
+def fpp_server_destroy(sv):
+    if sv is not None and sv.value:
+        lib().fpp_server_destroy(sv)
