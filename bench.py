@@ -4,8 +4,9 @@
 Workload (synthetic, seeded): n = 1,000,000 points, d = 128, a 1,000-centre Gaussian mixture on
 the unit sphere (spread 0.3); 10,000 queries from the same mixture; L = 100 tables of two
 concatenated cross-polytope hashes, D = 128 (65,536 buckets per table), alpha = 0.3, iProbes = 3;
-k = 10. The per-table probe budget is the smallest of 10, 20, 50, 100, 200 whose recall@10 on a
-1,000-query sample reaches 0.9 (qProbes passed to the library = budget x L).
+k = 10. qProbes (the total over all tables) is the smallest of 10, 20, 50, ..., 20,000 whose
+recall@10 on a 1,000-query sample reaches 0.9; the sweep covers the workload's values read both
+as totals (10..200) and as per-table budgets (x L = 1,000..20,000).
 
 A step is one pass of the query path over the 10,000 resident queries (hash -> probe selection
 -> gather/score/top-k [-> FP32 rerank]); the index build is timed separately. `value` is the
@@ -29,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-QPT_SWEEP = (10, 20, 50, 100, 200)
+QP_SWEEP = (10, 20, 50, 100, 200, 500, 1000, 2000, 5000, 10000, 20000)
 
 
 def log(*a):
@@ -173,7 +174,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--qpt", type=int, default=0, help="probes per table (0 = sweep for recall >= 0.9)")
+    ap.add_argument("--qprobes", type=int, default=0, help="total probes per query (0 = sweep for recall >= 0.9)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-queries", type=int, default=60_000)
@@ -213,25 +214,25 @@ def main():
     chosen = {}
     recalls = {}
     for store in ("fp32", "bf16"):
-        for qpt in ([args.qpt] if args.qpt else QPT_SWEEP):
-            ids, _ = F.fpp_query(h, Qd[:ns].contiguous(), k, qpt * w.L, store=store)
+        for qp in ([args.qprobes] if args.qprobes else QP_SWEEP):
+            ids, _ = F.fpp_query(h, Qd[:ns].contiguous(), k, qp, store=store)
             r = recall_at_10(ids.cpu().numpy(), truth)
-            recalls[f"{store}@{qpt}"] = round(r, 4)
-            log(f"recall {store} qpt={qpt}: {r:.4f}")
+            recalls[f"{store}@{qp}"] = round(r, 4)
+            log(f"recall {store} qProbes={qp}: {r:.4f}")
             if r >= 0.9 and store not in chosen:
-                chosen[store] = qpt
+                chosen[store] = qp
                 break
-        chosen.setdefault(store, args.qpt or QPT_SWEEP[-1])
+        chosen.setdefault(store, args.qprobes or QP_SWEEP[-1])
 
     res = {}
     for store in ("fp32", "bf16"):
-        qp = chosen[store] * w.L
+        qp = chosen[store]
         ms, stage = timed_steps(torch, F, h, Qd, k, qp, store, args.steps, args.warmup)
         _, _, st = F.fpp_query(h, Qd, k, qp, store=store, stats=True)
         st = st.cpu().numpy()
         R = max(100, 2 * k)
         byt = algorithmic_bytes(st, w.X.shape[1], store, k, R)
-        res[store] = dict(ms_per_step=ms, qps=w.Q.shape[0] / (ms / 1e3), qpt=chosen[store],
+        res[store] = dict(ms_per_step=ms, qps=w.Q.shape[0] / (ms / 1e3), qprobes=chosen[store],
                           stage_ms=[round(x, 4) for x in stage], bytes=byt,
                           gbs=byt / (stage[2] / 1e3) / 1e9,
                           probes=float(st[:, 0].mean()), entries=float(st[:, 1].mean()),
@@ -242,22 +243,34 @@ def main():
     serving = {}
     if not args.no_serving:
         cap = res["bf16"]["qps"]
-        qp = chosen["bf16"] * w.L
+        qp = chosen["bf16"]
         for frac in (0.25, 0.5, 0.8):
             r = serving_run(torch, F, h, Qd, store="bf16", qps_offered=frac * cap,
                             n_queries=args.serving_queries, k_choices=(k,), qp_choices=(qp,), seed=1)
             serving[f"{frac}"] = r
             log(f"serving {frac:.2f}x: offered {r['offered_qps']:.0f} achieved {r['achieved_qps']:.0f} "
                 f"p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms batches {r['batches']}")
-        mixed = serving_run(torch, F, h, Qd, store="bf16", qps_offered=0.25 * cap, n_queries=args.serving_queries,
+        # mixed requests (k in {1, 10, 100}, 20/50/200 probes per table): offered at half the
+        # capacity a batch of that mix reaches
+        rng = np.random.default_rng(3)
+        mk = rng.choice([1, 10, 100], size=w.Q.shape[0])
+        mq = rng.choice([20 * w.L, 50 * w.L, 200 * w.L], size=w.Q.shape[0])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        F.fpp_query_batch(h, Qd, mk, mq, store="bf16")
+        torch.cuda.synchronize()
+        mixed_cap = w.Q.shape[0] / (time.perf_counter() - t)
+        mixed = serving_run(torch, F, h, Qd, store="bf16", qps_offered=0.5 * mixed_cap,
+                            n_queries=min(args.serving_queries, 20_000),
                             k_choices=(1, 10, 100), qp_choices=(20 * w.L, 50 * w.L, 200 * w.L), seed=2)
+        mixed["batch_capacity_qps"] = mixed_cap
         serving["mixed_k_qprobes"] = mixed
         log(f"serving mixed: achieved {mixed['achieved_qps']:.0f} p50 {mixed['p50_ms']:.2f} p99 {mixed['p99_ms']:.2f}")
 
     cpu = None
     if not args.no_cpu_baseline:
         t = time.perf_counter()
-        cpu = cpu_baseline(w, chosen["fp32"], k)
+        cpu = cpu_baseline(w, max(1, -(-chosen["fp32"] // w.L)), k)
         log(f"cpu baseline {cpu['value']:.2f} q/s in {time.perf_counter() - t:.1f}s")
 
     head = res["bf16"]
@@ -283,11 +296,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": "c2_cluster_1m_d128: n=1,000,000 d=128 1000-centre mixture spread 0.3; "
                                "L=100 D=128 l=2 alpha=0.3 iProbes=3; 10,000 queries k=10",
-                   "global_batch": int(w.Q.shape[0]), "probes_per_table": chosen["bf16"],
-                   "qProbes": chosen["bf16"] * w.L, "store": "bf16 + fp32 rerank of 100"},
+                   "global_batch": int(w.Q.shape[0]), "qProbes": chosen["bf16"],
+                   "store": "bf16 + fp32 rerank of 100"},
         "recall@10": recalls.get(f"bf16@{chosen['bf16']}"),
         "fp32_batch": {"qps": round(res["fp32"]["qps"], 1), "ms_per_step": round(res["fp32"]["ms_per_step"], 4),
-                       "probes_per_table": chosen["fp32"], "recall@10": recalls.get(f"fp32@{chosen['fp32']}"),
+                       "qProbes": chosen["fp32"], "recall@10": recalls.get(f"fp32@{chosen['fp32']}"),
                        "stage_ms": res["fp32"]["stage_ms"], "gather_gbs": round(res["fp32"]["gbs"], 1)},
         "bf16_batch": {"stage_ms": head["stage_ms"], "unique_per_query": head["unique"],
                        "entries_per_query": head["entries"]},

@@ -25,65 +25,112 @@ __device__ __forceinline__ float flip(float v, uint32_t mask) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Query side. One wavefront per (vector, function): the rotation runs in LDS with the same
-// butterfly order, then the D (|y|, i) keys are bitonic-sorted in LDS, descending by
-// (|y| bits << 32 | ~i), which is (|y| desc, i asc).
+// Query side. One wavefront per (vector, function), everything in registers: lane x holds the
+// elements j = e * 64 + x (e < E = P / 64; for P < 64 lanes x < P hold one element). Butterfly
+// stages h < 64 pair lane x with lane x ^ h (the lower lane adds, the upper subtracts), stages
+// h >= 64 pair register e with e ^ (h / 64) inside the lane, in the order h = 1, 2, ..., P/2.
+// The D keys (|y_i| bits << 32 | (0xffff - i) << 1 | sign) are then bitonic-sorted descending in
+// the same layout, which orders the list by (|y| desc, i asc) and carries the code bit.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void hash_query_kernel(
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void hash_query_kernel(
     const float* __restrict__ V, int64_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
-    int LF, int P, int D, int Dp2, float* __restrict__ la, uint16_t* __restrict__ lc) {
-  extern __shared__ unsigned char smem[];
-  float* v = reinterpret_cast<float*>(smem);                        // [P]
-  uint64_t* key = reinterpret_cast<uint64_t*>(smem + (size_t)P * 4);   // [Dp2], 8-byte aligned (P >= 2)
-  const int lane = threadIdx.x;
-  const int64_t item = blockIdx.x;   // vector * LF + function
+    int LF, int D, float* __restrict__ la, uint16_t* __restrict__ lc) {
+  constexpr int E = P >= 64 ? P / 64 : 1;
+  constexpr int XS = P >= 64 ? 64 : P;   // lanes that hold elements
+  const int lane = threadIdx.x & 63;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (item >= m * LF) return;   // whole wavefront
   const int64_t q = item / LF;
   const int tf = (int)(item - q * LF);
-  if (q >= m) return;   // uniform for the block
+  const bool on = lane < XS;
 
-  for (int j = lane; j < P; j += 64) v[j] = j < d ? V[q * ldv + j] : 0.0f;
-  __syncthreads();
+  float v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int j = e * 64 + lane;
+    v[e] = (on && j < d) ? V[q * ldv + j] : 0.0f;
+  }
   const uint32_t* sm = sign_mask + (size_t)tf * 3 * P;
   for (int r = 0; r < 3; ++r) {
-    for (int j = lane; j < P; j += 64) v[j] = flip(v[j], sm[r * P + j]);
-    __syncthreads();
-    for (int h = 1; h < P; h <<= 1) {
-      for (int b = lane; b < P / 2; b += 64) {
-        const int j = (b / h) * 2 * h + (b % h);
-        const float a = v[j], c = v[j + h];
-        v[j] = a + c;
-        v[j + h] = a - c;
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (on) v[e] = flip(v[e], sm[r * P + e * 64 + lane]);
+#pragma unroll
+    for (int h = 1; h < XS; h <<= 1) {
+      const bool upper = (lane & h) != 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const float w = __shfl_xor(v[e], h);
+        v[e] = upper ? w - v[e] : v[e] + w;
       }
-      __syncthreads();
+    }
+#pragma unroll
+    for (int hh = 1; hh < E; hh <<= 1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if ((e & hh) == 0) {
+          const float a = v[e], b = v[e + hh];
+          v[e] = a + b;
+          v[e + hh] = a - b;
+        }
+      }
     }
   }
-  for (int i = lane; i < Dp2; i += 64)
-    key[i] = i < D ? ((uint64_t)__float_as_uint(fabsf(v[i])) << 32) | (uint32_t)(0xffffffffu - i)
-                   : 0ull;
-  __syncthreads();
-  for (int k = 2; k <= Dp2; k <<= 1) {
+  uint64_t key[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = e * 64 + lane;
+    const uint32_t neg = v[e] >= 0.0f ? 0u : 1u;
+    key[e] = (on && i < D) ? ((uint64_t)__float_as_uint(fabsf(v[e])) << 32) |
+                                 ((uint32_t)(0xffff - i) << 1) | neg
+                           : 0ull;
+  }
+  // bitonic sort (descending) of the first D keys, D a power of two
+  for (int k = 2; k <= D; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < Dp2; i += 64) {
-        const int ixj = i ^ j;
-        if (ixj > i) {
-          const uint64_t a = key[i], b = key[ixj];
-          const bool desc = (i & k) == 0;
-          if (desc ? (a < b) : (a > b)) {
-            key[i] = b;
-            key[ixj] = a;
+      if (j < 64) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = e * 64 + lane;
+          const uint64_t o = shfl_xor_u64(key[e], j);
+          const bool lower = (i & j) == 0, desc = (i & k) == 0;
+          const uint64_t mx = key[e] > o ? key[e] : o, mn = key[e] > o ? o : key[e];
+          key[e] = (lower == desc) ? mx : mn;
+        }
+      } else {
+        const int jj = j >> 6;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if ((e & jj) == 0 && (e | jj) < E) {
+            const int i = e * 64 + lane;
+            const bool desc = (i & k) == 0;
+            const uint64_t a = key[e], b = key[e | jj];
+            if (desc ? (a < b) : (a > b)) {
+              key[e] = b;
+              key[e | jj] = a;
+            }
           }
         }
       }
-      __syncthreads();
     }
   }
   float* ola = la + (size_t)item * D;
   uint16_t* olc = lc + (size_t)item * D;
-  for (int i = lane; i < D; i += 64) {
-    const uint64_t kk = key[i];
-    const int idx = (int)(0xffffffffu - (uint32_t)kk);
-    ola[i] = __uint_as_float((uint32_t)(kk >> 32));
-    olc[i] = (uint16_t)(v[idx] >= 0.0f ? idx : idx + D);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = e * 64 + lane;
+    if (on && p < D) {
+      const uint64_t kk = key[e];
+      const int idx = 0xffff - (int)(((uint32_t)kk & 0x1ffffu) >> 1);
+      ola[p] = __uint_as_float((uint32_t)(kk >> 32));
+      olc[p] = (uint16_t)((kk & 1u) ? idx + D : idx);
+    }
   }
 }
 
@@ -105,13 +152,20 @@ hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_
 hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int ldv, float* la,
                              uint16_t* lc, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  int Dp2 = 1;
-  while (Dp2 < ix->D) Dp2 <<= 1;
   const int LF = ix->L * ix->l;
-  const size_t lds = (size_t)ix->P * 4 + (size_t)Dp2 * 8;
   const int64_t items = m * LF;
-  hipLaunchKernelGGL(hash_query_kernel, dim3((unsigned)items), dim3(64), lds, s, V, m, ldv, ix->d,
-                     ix->sign_mask, LF, ix->P, ix->D, Dp2, la, lc);
+  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
+#define FPP_HQ(PP)                                                                             \
+  case PP:                                                                                     \
+    hipLaunchKernelGGL(hash_query_kernel<PP>, grid, block, 0, s, V, m, ldv, ix->d, ix->sign_mask, \
+                       LF, ix->D, la, lc);                                                     \
+    break;
+  switch (ix->P) {
+    FPP_HQ(2) FPP_HQ(4) FPP_HQ(8) FPP_HQ(16) FPP_HQ(32) FPP_HQ(64) FPP_HQ(128) FPP_HQ(256)
+    FPP_HQ(512) FPP_HQ(1024) FPP_HQ(2048) FPP_HQ(4096)
+    default: return hipErrorInvalidValue;
+  }
+#undef FPP_HQ
   return hipGetLastError();
 }
 

@@ -11,88 +11,165 @@
 //     count_ge(next(tau*)) < qProbes <= count_ge(tau*);
 //   * every pair with s > tau* is taken, then the first pairs with s == tau* in
 //     (table, i, j) order until qProbes are selected.
-// One wavefront per query; lane x walks tables x, x + 64, ...
+// One workgroup per query; thread x walks tables x, x + 128, ... with the first M entries of
+// every sorted list staged in LDS (entries past M are read from device memory).
 #include "fpp_internal.hpp"
 
 namespace fpp {
 namespace {
 
-__device__ __forceinline__ uint64_t count_table(const float* A, const float* B, int l, int D,
-                                                float tau) {
+constexpr int kProbeThreads = 128;
+constexpr int kProbeWaves = kProbeThreads / 64;
+
+// Sorted-list access: the first M entries of every list of the query sit in LDS.
+struct Lists {
+  const float* lds;     // [LF][M]
+  const float* glob;    // [LF][D] of this query
+  int M, D;
+  __device__ __forceinline__ float get(int list, int i) const {
+    return i < M ? lds[list * M + i] : glob[(size_t)list * D + i];
+  }
+};
+
+// min(cap, #pairs of table t with score >= tau); A = list 2t (or t for l = 1), B = list 2t + 1.
+// The walk stops once `cap` pairs are counted, so its depth is bounded by cap.
+__device__ __forceinline__ uint64_t count_table(const Lists& ls, int t, int l, float tau,
+                                                uint64_t cap) {
+  const int D = ls.D;
+  const int lim = cap < (uint64_t)D ? (int)cap : D;
   if (l == 1) {
     int c = 0;
-    while (c < D && A[c] >= tau) ++c;
+    while (c < lim && ls.get(t, c) >= tau) ++c;
     return (uint64_t)c;
   }
+  const int la = 2 * t, lb = 2 * t + 1;
+  const float a0 = ls.get(la, 0);
   int j = 0;
-  const float a0 = A[0];
-  while (j < D && a0 + B[j] >= tau) ++j;
+  while (j < lim && a0 + ls.get(lb, j) >= tau) ++j;
   uint64_t c = 0;
   for (int i = 0; i < D && j > 0; ++i) {
-    const float ai = A[i];
-    while (j > 0 && !(ai + B[j - 1] >= tau)) --j;
+    const float ai = ls.get(la, i);
+    while (j > 0 && !(ai + ls.get(lb, j - 1) >= tau)) --j;
     c += (uint64_t)j;
+    if (c >= cap) return cap;
   }
-  return c;
+  return c < cap ? c : cap;
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+__device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  uint64_t t = 0;
+#pragma unroll
+  for (int i = 0; i < kProbeWaves; ++i) t += red[i];
+  __syncthreads();
+  return t;
 }
 
-__device__ __forceinline__ uint64_t wave_excl_scan_u64(uint64_t v, uint64_t& total) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ float block_max(float v, float* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  float t = red[0];
+#pragma unroll
+  for (int i = 1; i < kProbeWaves; ++i) t = fmaxf(t, red[i]);
+  __syncthreads();
+  return t;
+}
+
+// Exclusive scan over the block (thread order); returns the prefix and the block total.
+__device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t& total, uint64_t* red) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint64_t inc = v;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const uint64_t t = __shfl_up(inc, o);
     if (lane >= o) inc += t;
   }
-  total = __shfl(inc, 63);
-  return inc - v;
+  if (lane == 63) red[w] = inc;
+  __syncthreads();
+  uint64_t before = 0;
+  total = 0;
+#pragma unroll
+  for (int i = 0; i < kProbeWaves; ++i) {
+    if (i < w) before += red[i];
+    total += red[i];
+  }
+  __syncthreads();
+  return before + inc - v;
 }
 
-__global__ __launch_bounds__(256) void probe_kernel(
+// One workgroup per query; thread x walks tables x, x + 128, ...
+__global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     const float* __restrict__ la, const uint16_t* __restrict__ lc, int64_t m, int L, int l, int D,
-    int64_t NB, const int32_t* __restrict__ qp_arr, int32_t qp_uniform, int32_t qcap,
+    int M, int64_t NB, const int32_t* __restrict__ qp_arr, int32_t qp_uniform, int32_t qcap,
     uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
-  const int lane = threadIdx.x & 63;
-  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (q >= m) return;   // whole wavefront
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* red = reinterpret_cast<uint64_t*>(smem);        // kProbeWaves words
+  float* pre = reinterpret_cast<float*>(smem + 64);         // [LF][M]
+  const int64_t q = blockIdx.x;
+  if (q >= m) return;   // uniform
+  const int tid = threadIdx.x;
   const int LF = L * l;
   const float* Aq = la + (size_t)q * LF * D;
   const uint16_t* Cq = lc + (size_t)q * LF * D;
+  for (int i = tid; i < LF * M; i += kProbeThreads) {
+    const int list = i / M, e = i - list * M;
+    pre[i] = Aq[(size_t)list * D + e];
+  }
+  __syncthreads();
+  const Lists ls{pre, Aq, M, D};
+
   const uint64_t total = (uint64_t)L * (l == 1 ? (uint64_t)D : (uint64_t)D * D);
-  int64_t want = qp_arr ? qp_arr[q] : qp_uniform;
+  const int64_t want = qp_arr ? qp_arr[q] : qp_uniform;
   uint64_t qP = want < 1 ? 0 : ((uint64_t)want < total ? (uint64_t)want : total);
   if (qP > (uint64_t)qcap) qP = (uint64_t)qcap;
   if (qP == 0) {
-    if (lane == 0) nprobe[q] = 0;
+    if (tid == 0) nprobe[q] = 0;
     return;
   }
-
-  float mx = 0.0f;
-  for (int t = lane; t < L; t += 64) {
-    const float* A = Aq + (size_t)t * l * D;
-    const float s = l == 1 ? A[0] : A[0] + A[D];
-    mx = fmaxf(mx, s);
+  // Bracket. hi: just above the best pair of all tables (no pair reaches it). lo: with
+  // c = ceil(qP / L), every table has at least c pairs scoring >= its bound (row 0 for c <= D,
+  // else the first ceil(c / D) full rows), so the minimum bound over tables counts >= L c >= qP.
+  const uint64_t cpt = (qP + L - 1) / L;
+  float mx = 0.0f, mn = INFINITY;
+  for (int t = tid; t < L; t += kProbeThreads) {
+    float top, bound;
+    if (l == 1) {
+      top = ls.get(t, 0);
+      bound = cpt <= (uint64_t)D ? ls.get(t, (int)cpt - 1) : 0.0f;
+    } else {
+      top = ls.get(2 * t, 0) + ls.get(2 * t + 1, 0);
+      if (cpt <= (uint64_t)D) {
+        bound = ls.get(2 * t, 0) + ls.get(2 * t + 1, (int)cpt - 1);
+      } else {
+        const uint64_t rows = (cpt + D - 1) / D;
+        bound = rows <= (uint64_t)D ? ls.get(2 * t, (int)rows - 1) + ls.get(2 * t + 1, D - 1) : 0.0f;
+      }
+    }
+    mx = fmaxf(mx, top);
+    mn = fminf(mn, bound);
   }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
-  uint32_t lo = 0u, hi = __float_as_uint(mx) + 1u;   // count_ge(lo) >= qP > count_ge(hi)
+  mx = block_max(mx, reinterpret_cast<float*>(red));
+  mn = -block_max(-mn, reinterpret_cast<float*>(red));
+
+  // Counts are capped at qP + 1 per table: a capped sum is >= qP exactly when the true sum is,
+  // and equals qP only when no table was capped, so every decision below is the uncapped one.
+  const uint64_t cap = qP + 1;
+  uint32_t lo = __float_as_uint(mn), hi = __float_as_uint(mx) + 1u;   // cnt(lo) >= qP > cnt(hi)
   uint64_t c_hi = 0;
   bool exact = false;
   while (hi - lo > 1u) {
     const uint32_t mid = lo + (hi - lo) / 2u;
     const float tau = __uint_as_float(mid);
     uint64_t c = 0;
-    for (int t = lane; t < L; t += 64) {
-      const float* A = Aq + (size_t)t * l * D;
-      c += count_table(A, A + D, l, D, tau);
-    }
-    c = wave_sum_u64(c);
+    for (int t = tid; t < L; t += kProbeThreads) c += count_table(ls, t, l, tau, cap);
+    c = block_sum_u64(c, red);
     if (c == qP) {
       lo = mid;
       exact = true;
@@ -105,7 +182,6 @@ __global__ __launch_bounds__(256) void probe_kernel(
       c_hi = c;
     }
   }
-  // take every pair with s >= thr_gt, then `need` ties at s == tau_eq in (t, i, j) order
   const float thr_gt = __uint_as_float(exact ? lo : hi);
   const float tau_eq = __uint_as_float(lo);
   const uint64_t c_gt = exact ? qP : c_hi;
@@ -115,60 +191,73 @@ __global__ __launch_bounds__(256) void probe_kernel(
   const int twoD = 2 * D;
 
   uint64_t run_gt = 0, run_eq = 0;
-  for (int tb = 0; tb < L; tb += 64) {
-    const int t = tb + lane;
-    const float* A = Aq + (size_t)t * l * D;
-    const float* B = A + D;
+  for (int tb = 0; tb < L; tb += kProbeThreads) {
+    const int t = tb + tid;
     uint64_t n_gt = 0, n_eq = 0;
     if (t < L) {
-      n_gt = count_table(A, B, l, D, thr_gt);
-      if (need) n_eq = count_table(A, B, l, D, tau_eq) - n_gt;
+      // every table holds at most c_gt <= qP pairs above thr_gt; ties are only needed up to `need`
+      n_gt = count_table(ls, t, l, thr_gt, cap);
+      if (need) n_eq = count_table(ls, t, l, tau_eq, n_gt + need) - n_gt;
     }
     uint64_t tot_gt, tot_eq;
-    const uint64_t pos_gt0 = run_gt + wave_excl_scan_u64(n_gt, tot_gt);
-    const uint64_t tie0 = run_eq + wave_excl_scan_u64(n_eq, tot_eq);
+    const uint64_t pos_gt0 = run_gt + block_scan_u64(n_gt, tot_gt, red);
+    const uint64_t tie0 = run_eq + block_scan_u64(n_eq, tot_eq, red);
     run_gt += tot_gt;
     run_eq += tot_eq;
     if (t >= L) continue;
-    const uint16_t* C1 = Cq + (size_t)t * l * D;
-    const uint16_t* C2 = C1 + D;
     const uint32_t tbase = (uint32_t)((int64_t)t * stride);
     uint64_t pg = pos_gt0, te = tie0;
     if (l == 1) {
+      const uint16_t* C1 = Cq + (size_t)t * D;
       for (uint64_t i = 0; i < n_gt; ++i) out[pg++] = tbase + C1[i];
-      for (uint64_t i = n_gt; i < n_gt + n_eq && te < need; ++i, ++te)
-        out[c_gt + te] = tbase + C1[i];
+      for (uint64_t i = n_gt; i < n_gt + n_eq && te < need; ++i, ++te) out[c_gt + te] = tbase + C1[i];
       continue;
     }
-    // two thresholds walked together: jg for s >= thr_gt, je for s >= tau_eq (je >= jg)
+    const uint16_t* C1 = Cq + (size_t)(2 * t) * D;
+    const uint16_t* C2 = C1 + D;
+    const int la_ = 2 * t, lb_ = 2 * t + 1;
     int jg = 0, je = 0;
-    const float a0 = A[0];
-    while (jg < D && a0 + B[jg] >= thr_gt) ++jg;
+    const float a0 = ls.get(la_, 0);
+    while (jg < D && a0 + ls.get(lb_, jg) >= thr_gt) ++jg;
     if (need) {
       je = jg;
-      while (je < D && a0 + B[je] >= tau_eq) ++je;
+      while (je < D && a0 + ls.get(lb_, je) >= tau_eq) ++je;
     }
     for (int i = 0; i < D && (jg > 0 || je > 0); ++i) {
-      const float ai = A[i];
-      while (jg > 0 && !(ai + B[jg - 1] >= thr_gt)) --jg;
+      const float ai = ls.get(la_, i);
+      while (jg > 0 && !(ai + ls.get(lb_, jg - 1) >= thr_gt)) --jg;
       if (need)
-        while (je > 0 && !(ai + B[je - 1] >= tau_eq)) --je;
+        while (je > 0 && !(ai + ls.get(lb_, je - 1) >= tau_eq)) --je;
       const uint32_t rowb = tbase + (uint32_t)C1[i] * twoD;
       for (int j = 0; j < jg; ++j) out[pg++] = rowb + C2[j];
       for (int j = jg; j < je && te < need; ++j, ++te) out[c_gt + te] = rowb + C2[j];
     }
   }
-  if (lane == 0) nprobe[q] = (int32_t)qP;
+  if (tid == 0) nprobe[q] = (int32_t)qP;
 }
 
 }  // namespace
+
+// Prefix length of each sorted list staged in LDS: enough for about twice the average number of
+// probes per table, at most D and at most 60 KB of LDS per query.
+int probe_prefix(const fpp_index* ix, int32_t qcap) {
+  const int LF = ix->L * ix->l;
+  int want = 16;
+  const int64_t per_t = (2LL * qcap + ix->L - 1) / ix->L;
+  while (want < per_t && want < ix->D) want <<= 1;
+  if (want > ix->D) want = ix->D;
+  while (want > 1 && (int64_t)LF * want * 4 > 60 * 1024) want >>= 1;
+  return want;
+}
 
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc, int64_t m,
                                const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
                                uint32_t* probes, int32_t* nprobe, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  hipLaunchKernelGGL(probe_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, s, la, lc, m,
-                     ix->L, ix->l, ix->D, ix->NB, qp_arr, qp_uniform, qcap, probes, nprobe);
+  const int M = probe_prefix(ix, qcap);
+  const size_t lds = 64 + (size_t)ix->L * ix->l * M * 4;
+  hipLaunchKernelGGL(probe_kernel, dim3((unsigned)m), dim3(kProbeThreads), lds, s, la, lc, m, ix->L,
+                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probes, nprobe);
   return hipGetLastError();
 }
 
