@@ -253,15 +253,19 @@ int32_t short_list_len(int32_t R_opt, int32_t k) {
 
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
+size_t overflow_bitmap_bytes(const fpp_index* ix) {
+  return (size_t)score_grid_blocks(ix) * (size_t)((ix->n + 31) / 32) * 4;
+}
+
 Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max,
-                          int32_t store, int32_t R_opt, int64_t budget) {
+                          int32_t store, int32_t R_opt, int64_t budget, bool gbm_in_scratch) {
   Layout ly;
   ly.qcap = (int32_t)std::min<int64_t>(std::max(qp_max, 1), total_pairs(ix));
   ly.short_ld = store == FPP_STORE_FP32 ? 0 : short_list_len(R_opt, k_max);
   const int64_t LF = (int64_t)ix->L * ix->l;
   const int64_t per_q = LF * ix->D * 6 + (int64_t)ly.qcap * 4 + 4 + (int64_t)ly.short_ld * 4 + 64;
   ly.mc = std::max<int64_t>(1, std::min<int64_t>(m, budget / per_q));
-  ly.gbm = !score_bitmap_in_lds(ix);
+  ly.gbm = gbm_in_scratch;
   ly.grid = score_grid_blocks(ix);
   size_t o = 0;
   ly.off_la = o;
@@ -275,7 +279,7 @@ Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max
   ly.off_short = o;
   o = a256(o + (size_t)ly.mc * ly.short_ld * 4);
   ly.off_gbm = o;
-  if (ly.gbm) o = a256(o + (size_t)ly.grid * ((ix->n + 31) / 32) * 4);
+  if (ly.gbm) o = a256(o + overflow_bitmap_bytes(ix));
   ly.total = o;
   return ly;
 }
@@ -305,7 +309,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
   uint32_t* probes = (uint32_t*)(ws + ly.off_probes);
   int32_t* np = (int32_t*)(ws + ly.off_np);
   int32_t* shortl = (int32_t*)(ws + ly.off_short);
-  uint32_t* gbm = ly.gbm ? (uint32_t*)(ws + ly.off_gbm) : nullptr;
+  uint32_t* gbm = ly.gbm ? (uint32_t*)(ws + ly.off_gbm) : qs.gbm_ext;
   const int d = ix->d;
   for (int64_t c0 = 0; c0 < qs.m; c0 += ly.mc) {
     const int64_t mc = std::min<int64_t>(ly.mc, qs.m - c0);
@@ -329,7 +333,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     a.rerank_R = qs.R_opt;
     a.stats = qs.stats ? qs.stats + c0 * 3 : nullptr;
     a.gbitmap = gbm;
-    a.grid = (int32_t)std::min<int64_t>(ly.grid, mc);
+    a.grid = ly.grid;
     a.short_ids = shortl;
     a.short_ld = ly.short_ld;
     int32_t* ids_c = qs.ids_out;

@@ -133,7 +133,7 @@ struct ScoreArgs {
   int32_t* short_ids;      // [m][short_ld] short lists (low-precision stores)
   int32_t short_ld;
   int64_t* stats;          // [m][3] or null
-  uint32_t* gbitmap;       // global dedup bitmaps (large n), [grid][ceil(n/32)] or null
+  uint32_t* gbitmap;       // overflow dedup bitmaps [grid][ceil(n/32)], zero on entry and exit
   int32_t grid;            // persistent blocks
 };
 hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s);
@@ -143,7 +143,6 @@ hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m
                          float* scores_out, hipStream_t s);
 int score_grid_blocks(const fpp_index* ix);
 int32_t short_list_len(int32_t R_opt, int32_t k);
-bool score_bitmap_in_lds(const fpp_index* ix);
 
 // ----------------------------------------------------------------------------------------------
 // Query pipeline (api.cpp), shared with the serving loop
@@ -164,13 +163,14 @@ struct QuerySpec {
   float* scores_out = nullptr;
   int64_t* stats = nullptr;
   double* stage_ms = nullptr;          // host [4] or null
+  uint32_t* gbm_ext = nullptr;         // caller-owned zeroed overflow bitmaps, or null (scratch)
 };
 
 struct Layout {
   int64_t mc = 0;         // queries per chunk
   int32_t qcap = 0;       // probes per query
   int32_t short_ld = 0;   // short-list row length
-  bool gbm = false;       // global dedup bitmaps
+  bool gbm = false;       // overflow bitmaps live in the scratch (else the caller provides them)
   int grid = 0;
   size_t off_la = 0, off_lc = 0, off_probes = 0, off_np = 0, off_short = 0, off_gbm = 0, total = 0;
 };
@@ -181,7 +181,9 @@ int check_store(const fpp_index* ix, int32_t store);
 // Scratch layout for m queries; queries are processed in chunks so that one chunk's lists and
 // probes stay within `budget` bytes.
 Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max, int32_t store,
-                   int32_t R_opt, int64_t budget = (int64_t)1 << 30);
+                   int32_t R_opt, int64_t budget = (int64_t)1 << 30, bool gbm_in_scratch = true);
+// Bytes of the overflow bitmaps of one score launch.
+size_t overflow_bitmap_bytes(const fpp_index* ix);
 // Runs hash -> probe selection -> score (-> rerank) over [0, qs.m) with device scratch `ws`
 // laid out by `ly`. Per-query arrays of qs must already be on the device.
 // `ev` (optional) receives 5 events per chunk: before hashing, after hashing, after probe

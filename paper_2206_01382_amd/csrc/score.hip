@@ -1,18 +1,19 @@
 // Candidate gather, dedup, scoring and top-k on gfx950 (Section 3.4 multi-probe querying;
 // Section 1 problem statement: the answer is the top-k of x^T q).
 //
-// One persistent 1024-thread workgroup per CU walks queries q = blockIdx.x, + gridDim.x, ...
+// Persistent 256-thread workgroups (several per CU) walk queries q = blockIdx.x, + gridDim.x, ...
 // For each query:
-//   A. the probed CSR ranges are loaded 512 at a time and prefix-summed; every thread takes one
-//      entry, reads its id and test-and-sets the id's bit in an n-bit bitmap (in LDS when n fits,
-//      else a per-workgroup bitmap in device memory). First-time ids enter an LDS queue
-//      (set semantics: an id is scored once however many buckets hold it).
+//   A. the probed CSR ranges are loaded 256 at a time and prefix-summed; every thread takes four
+//      consecutive entries, reads their ids and inserts them into an LDS open-addressing set
+//      (set semantics: an id is scored once however many buckets hold it). Past 3072 distinct
+//      ids the workgroup moves the set into its n-bit bitmap in device memory and continues
+//      there. First-time ids enter an LDS queue.
 //   B. when the queue holds >= 1024 ids (and at the end) the waves score it: G lanes cover one
 //      row with 16-byte loads, each lane folds its chunks into a float32 partial in a fixed order,
 //      and a fixed xor-shuffle tree over the G lanes finishes the sum. Scores therefore do not
-//      depend on batching or on which wave computes them.
-//   C. candidates above the running k-th best key go to an LDS buffer that is bitonic-sorted and
-//      cut to the best kk whenever it fills; the final sort gives (score desc, id asc) order.
+//      depend on batching or on which workgroup computes them.
+//   C. candidates above the running kk-th best key go to an LDS buffer that is sorted and cut to
+//      the best kk whenever it fills; the final sort gives (score desc, id asc) order.
 // Keys are 64-bit: order-preserving float bits << 32 | (0xffffffff - id).
 // The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
 // scores exactly in float32 from the FP32 store.
@@ -21,13 +22,18 @@
 namespace fpp {
 namespace {
 
-constexpr int kBlock = 1024;
+constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
+constexpr int kEPT = 4;                         // entries per thread per dedup round
+constexpr int kRound = kBlock * kEPT;           // entries per dedup round
 constexpr int kQueueCap = 2048;
-constexpr int kQueueFlush = kQueueCap - kBlock;
-constexpr int kCandCap = 2048;
-constexpr int kProbeChunk = 512;
-constexpr int kLdsBitmapWords = 32768;   // 2^20 ids
+constexpr int kQueueFlush = kQueueCap - kRound; // flush before a round could overflow the queue
+constexpr int kCandCap = 1024;
+constexpr int kProbeChunk = kBlock;
+constexpr int kSetSlots = 8192;                 // LDS id set (open addressing), 2^13 slots
+constexpr int kSetLimit = kSetSlots / 2 - kRound;   // switch to the bitmap above this many ids
+constexpr uint32_t kEmpty = 0xffffffffu;
+constexpr int kBlocksPerCU = 3;                 // ~50 KB of LDS per workgroup
 
 template <int STORE>
 struct Elems;
@@ -127,11 +133,51 @@ __device__ __forceinline__ void load_query(const float* qrow, int d, int g,
     }
 }
 
-// Block-wide bitonic sort (descending) of n = power-of-two keys in LDS.
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic stages j = jtop, ..., 1 (jtop <= 64) of stage k on a 128-key chunk held as two keys per
+// lane (indices i0 = base + lane, i1 = i0 + 64).
+__device__ __forceinline__ void chunk_stages(uint64_t& a, uint64_t& b, int i0, int k, int jtop) {
+  const int lane = threadIdx.x & 63;
+  for (int j = jtop; j > 0; j >>= 1) {
+    if (j == 64) {
+      const bool desc = (i0 & k) == 0;
+      if (desc ? (a < b) : (a > b)) {
+        const uint64_t t = a;
+        a = b;
+        b = t;
+      }
+    } else {
+      const uint64_t oa = shfl_xor_u64(a, j), ob = shfl_xor_u64(b, j);
+      const bool lower = (lane & j) == 0;
+      const bool da = (i0 & k) == 0, db = ((i0 + 64) & k) == 0;
+      const uint64_t amx = a > oa ? a : oa, amn = a > oa ? oa : a;
+      const uint64_t bmx = b > ob ? b : ob, bmn = b > ob ? ob : b;
+      a = (lower == da) ? amx : amn;
+      b = (lower == db) ? bmx : bmn;
+    }
+  }
+}
+
+// Block-wide bitonic sort (descending) of n keys in LDS, n a power of two >= 128. Stages with a
+// partner distance below 128 run in registers (two keys per lane, shuffles), the others in LDS.
 __device__ void block_sort_desc(uint64_t* key, int n) {
-  for (int k = 2; k <= n; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int chunks = n >> 7;
+  for (int c = wave; c < chunks; c += kWaves) {
+    const int i0 = (c << 7) + lane;
+    uint64_t a = key[i0], b = key[i0 + 64];
+    for (int k = 2; k <= 128; k <<= 1) chunk_stages(a, b, i0, k, k >> 1);
+    key[i0] = a;
+    key[i0 + 64] = b;
+  }
+  __syncthreads();
+  for (int k = 256; k <= n; k <<= 1) {
+    for (int j = k >> 1; j >= 128; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += kBlock) {
         const int ixj = i ^ j;
         if (ixj > i) {
           const uint64_t a = key[i], b = key[ixj];
@@ -144,10 +190,24 @@ __device__ void block_sort_desc(uint64_t* key, int n) {
       }
       __syncthreads();
     }
+    for (int c = wave; c < chunks; c += kWaves) {
+      const int i0 = (c << 7) + lane;
+      uint64_t a = key[i0], b = key[i0 + 64];
+      chunk_stages(a, b, i0, k, 64);
+      key[i0] = a;
+      key[i0 + 64] = b;
+    }
+    __syncthreads();
   }
 }
 
-// Exclusive block scan of one u32 per thread (kBlock threads).
+__device__ __forceinline__ int sort_size(uint32_t c) {
+  int n = 128;
+  while ((uint32_t)n < c) n <<= 1;
+  return n;
+}
+
+// Exclusive block scan of one u32 per thread.
 __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total, uint32_t* wsum) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   uint32_t inc = v;
@@ -158,20 +218,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t& total,
   }
   if (lane == 63) wsum[w] = inc;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t r = 0;
-    for (int i = 0; i < kWaves; ++i) {
-      const uint32_t x = wsum[i];
-      wsum[i] = r;
-      r += x;
-    }
-    wsum[kWaves] = r;
+  uint32_t before = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kWaves; ++i) {
+    const uint32_t x = wsum[i];
+    before += i < w ? x : 0u;
+    tot += x;
   }
+  total = tot;
   __syncthreads();
-  const uint32_t out = wsum[w] + inc - v;
-  total = wsum[kWaves];
-  __syncthreads();
-  return out;
+  return before + inc - v;
+}
+
+__device__ __forceinline__ uint32_t set_hash(uint32_t id) {
+  return (id * 0x9E3779B1u) >> (32 - 13);   // kSetSlots = 2^13
 }
 
 struct ScoreParams {
@@ -199,7 +259,7 @@ struct ScoreParams {
   int32_t* short_ids;        // [m][short_ld]
   int32_t short_ld;
   int64_t* stats;
-  uint32_t* gbitmap;
+  uint32_t* gbitmap;         // [gridDim.x][bm_words], zero on entry and on exit
   int64_t bm_words;
 };
 
@@ -207,46 +267,60 @@ struct SharedState {
   uint32_t qcount;
   uint32_t ccount;
   uint32_t uniq;
-  uint32_t pad;
+  uint32_t overflow;
   uint64_t thr;
 };
 
 // LDS carve-up (byte offsets).
 constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 constexpr size_t kOffCand = 0;
-constexpr size_t kOffQueue = kOffCand + (size_t)kCandCap * 8;
+constexpr size_t kOffSet = kOffCand + (size_t)kCandCap * 8;
+constexpr size_t kOffQueue = kOffSet + (size_t)kSetSlots * 4;
 constexpr size_t kOffBeg = kOffQueue + (size_t)kQueueCap * 4;
 constexpr size_t kOffPre = kOffBeg + (size_t)kProbeChunk * 4;
 constexpr size_t kOffWsum = kOffPre + (size_t)(kProbeChunk + 1) * 4;
 constexpr size_t kOffState = align_up(kOffWsum + (size_t)(kWaves + 2) * 4, 8);
-constexpr size_t kOffBitmap = align_up(kOffState + sizeof(SharedState), 16);
+constexpr size_t kLdsBytes = align_up(kOffState + sizeof(SharedState), 16);
 
-template <int STORE, int G, int C, bool LDSBM>
+// Insert into the LDS set; returns true when the id was not there yet.
+__device__ __forceinline__ bool set_insert(uint32_t* set, uint32_t id) {
+  uint32_t h = set_hash(id);
+  for (;;) {
+    const uint32_t old = atomicCAS(&set[h], kEmpty, id);
+    if (old == kEmpty) return true;
+    if (old == id) return false;
+    h = (h + 1) & (kSetSlots - 1);
+  }
+}
+
+__device__ __forceinline__ bool bitmap_insert(uint32_t* bm, uint32_t id) {
+  const uint32_t bit = 1u << (id & 31);
+  return !(atomicOr(&bm[id >> 5], bit) & bit);
+}
+
+template <int STORE, int G, int C>
 __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
   constexpr int EPC = Elems<STORE>::kPerChunk;
   constexpr int U = 8 / C;                 // rows in flight per lane
   constexpr int RPI = 64 / G;              // rows per wave instruction
   constexpr int RPW = U * RPI;             // rows per wave pass
   constexpr int RPB = RPW * kWaves;        // rows per block pass
-  static_assert(RPB <= kCandCap / 2, "candidate buffer too small");
+  static_assert(RPB <= kCandCap / 4, "candidate buffer too small");
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* cand = reinterpret_cast<uint64_t*>(smem + kOffCand);
+  uint32_t* set = reinterpret_cast<uint32_t*>(smem + kOffSet);
   uint32_t* queue = reinterpret_cast<uint32_t*>(smem + kOffQueue);
   uint32_t* s_beg = reinterpret_cast<uint32_t*>(smem + kOffBeg);
   uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + kOffPre);
   uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + kOffWsum);
   SharedState* st = reinterpret_cast<SharedState*>(smem + kOffState);
-  uint32_t* bitmap = LDSBM ? reinterpret_cast<uint32_t*>(smem + kOffBitmap)
-                           : p.gbitmap + (size_t)blockIdx.x * p.bm_words;
+  uint32_t* bitmap = p.gbitmap + (size_t)blockIdx.x * p.bm_words;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane % G, sub = lane / G;
-  const int64_t bm_words = (p.n + 31) / 32;
 
-  if (LDSBM) {
-    for (int64_t w = tid; w < bm_words; w += kBlock) bitmap[w] = 0u;
-  }
+  for (int i = tid; i < kSetSlots; i += kBlock) set[i] = kEmpty;
   __syncthreads();
 
   for (int64_t q = blockIdx.x; q < p.m; q += gridDim.x) {
@@ -258,11 +332,27 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       st->qcount = 0;
       st->ccount = 0;
       st->uniq = 0;
+      st->overflow = 0;
       st->thr = 0;
     }
     __syncthreads();
 
-    // ---- scoring of the queued ids
+    // keep the best kk candidates (sorted) and raise the threshold
+    auto compact = [&]() {
+      const uint32_t c0 = st->ccount;
+      const int n = sort_size(c0);
+      for (int i = tid; i < n; i += kBlock)
+        if ((uint32_t)i >= c0) cand[i] = 0ull;
+      __syncthreads();
+      block_sort_desc(cand, n);
+      if (tid == 0) {
+        st->ccount = c0 < (uint32_t)kk ? c0 : (uint32_t)kk;
+        if (c0 >= (uint32_t)kk) st->thr = cand[kk - 1];
+      }
+      __syncthreads();
+    };
+
+    // ---- B: scoring of the queued ids
     auto score_queue = [&]() {
       const uint32_t rows = st->qcount;
       for (uint32_t pb = 0; pb < rows; pb += RPB) {
@@ -302,20 +392,8 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
           }
         }
         __syncthreads();
-        if (st->ccount > (uint32_t)(kCandCap - RPB)) {
-          const uint32_t c0 = st->ccount;
-          for (int i = tid; i < kCandCap; i += kBlock)
-            if ((uint32_t)i >= c0) cand[i] = 0ull;
-          __syncthreads();
-          block_sort_desc(cand, kCandCap);
-          if (tid == 0) {
-            st->ccount = c0 < (uint32_t)kk ? c0 : (uint32_t)kk;
-            if (c0 >= (uint32_t)kk) st->thr = cand[kk - 1];
-          }
-          __syncthreads();
-        }
+        if (st->ccount > (uint32_t)(kCandCap - RPB)) compact();
       }
-      __syncthreads();
       if (tid == 0) st->qcount = 0;
       __syncthreads();
     };
@@ -334,16 +412,18 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       }
       uint32_t ec;
       const uint32_t pre = block_excl_scan(len, ec, wsum);
-      if (tid < kProbeChunk) {
-        s_beg[tid] = beg;
-        s_pre[tid] = pre;
-      }
+      s_beg[tid] = beg;
+      s_pre[tid] = pre;
       if (tid == 0) s_pre[kProbeChunk] = ec;
       __syncthreads();
       entries += ec;
-      for (uint32_t e0 = 0; e0 < ec; e0 += kBlock) {
-        const uint32_t e = e0 + tid;
-        int32_t nid = -1;
+      for (uint32_t e0 = 0; e0 < ec; e0 += kRound) {
+        const bool ovf = st->overflow != 0;
+        // four consecutive entries per thread: one search, then a linear walk over the probes
+        const uint32_t e = e0 + (uint32_t)tid * kEPT;
+        int32_t idv[kEPT];
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) idv[u] = -1;
         if (e < ec) {
           int lo = 0, hi = npc;   // s_pre[lo] <= e < s_pre[hi]
           while (hi - lo > 1) {
@@ -351,27 +431,58 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
             if (s_pre[mid] <= e) lo = mid;
             else hi = mid;
           }
-          const int32_t id = p.ids[s_beg[lo] + (e - s_pre[lo])];
-          const uint32_t bit = 1u << (id & 31);
-          const uint32_t old = atomicOr(&bitmap[id >> 5], bit);
-          if (!(old & bit)) nid = id;
-        }
-        const uint64_t mask = __ballot(nid >= 0);
-        const uint32_t cnt = (uint32_t)__popcll(mask);
-        if (cnt) {
-          uint32_t basepos = 0;
-          if (lane == 0) {
-            basepos = atomicAdd(&st->qcount, cnt);
-            atomicAdd(&st->uniq, cnt);
-          }
-          basepos = __shfl(basepos, 0);
-          if (nid >= 0) {
-            const uint32_t rank = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            queue[basepos + rank] = (uint32_t)nid;
+#pragma unroll
+          for (int u = 0; u < kEPT; ++u) {
+            const uint32_t eu = e + u;
+            if (eu < ec) {
+              while (s_pre[lo + 1] <= eu) ++lo;
+              idv[u] = p.ids[s_beg[lo] + (eu - s_pre[lo])];
+            }
           }
         }
+        uint32_t fresh = 0;   // bit u: entry u is a first occurrence
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+          if (idv[u] >= 0) {
+            const bool f = ovf ? bitmap_insert(bitmap, (uint32_t)idv[u]) : set_insert(set, (uint32_t)idv[u]);
+            fresh |= f ? (1u << u) : 0u;
+          }
+        }
+        // enqueue first occurrences (wave prefix sum of per-lane counts)
+        const uint32_t cnt = (uint32_t)__popc(fresh);
+        uint32_t inc = cnt;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t t = __shfl_up(inc, o);
+          if (lane >= o) inc += t;
+        }
+        const uint32_t wtot = __shfl(inc, 63);
+        uint32_t basepos = 0;
+        if (lane == 63 && wtot) {
+          basepos = atomicAdd(&st->qcount, wtot);
+          atomicAdd(&st->uniq, wtot);
+        }
+        basepos = __shfl(basepos, 63);
+        uint32_t pos = basepos + inc - cnt;
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u)
+          if (fresh & (1u << u)) queue[pos++] = (uint32_t)idv[u];
         __syncthreads();
         if (st->qcount >= (uint32_t)kQueueFlush) score_queue();
+        if (!st->overflow && st->uniq > (uint32_t)kSetLimit) {
+          // move the set into the device bitmap; later entries are tested there
+          for (int i = tid; i < kSetSlots; i += kBlock) {
+            const uint32_t v = set[i];
+            if (v != kEmpty) {
+              atomicOr(&bitmap[v >> 5], 1u << (v & 31));
+              set[i] = kEmpty;
+            }
+          }
+          __threadfence_block();
+          __syncthreads();
+          if (tid == 0) st->overflow = 1;
+          __syncthreads();
+        }
       }
       __syncthreads();
     }
@@ -379,11 +490,8 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
 
     // ---- C: final order and output
     {
+      compact();
       const uint32_t c0 = st->ccount;
-      for (int i = tid; i < kCandCap; i += kBlock)
-        if ((uint32_t)i >= c0) cand[i] = 0ull;
-      __syncthreads();
-      block_sort_desc(cand, kCandCap);
       if (!p.lowp) {
         const int64_t o = p.out_off ? p.out_off[q] : q * (int64_t)k;
         for (int r = tid; r < k; r += kBlock) {
@@ -405,10 +513,9 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       }
     }
 
-    // ---- clear the dedup bitmap
-    if (LDSBM) {
-      for (int64_t w = tid; w < bm_words; w += kBlock) bitmap[w] = 0u;
-    } else {
+    // ---- clear the dedup state
+    if (st->overflow) {
+      // every entry's word: the bitmap returns to zero
       for (int32_t pc = 0; pc < np; pc += kProbeChunk) {
         const int npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
         for (int i = wave; i < npc; i += kWaves) {
@@ -417,7 +524,10 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
           for (uint32_t e = b0 + lane; e < b1; e += 64) bitmap[p.ids[e] >> 5] = 0u;
         }
       }
-      __threadfence_block();
+      __threadfence();
+    } else {
+      // the set holds exactly the query's distinct ids (at most kSetLimit + kRound): reset slots
+      for (int i = tid; i < kSetSlots; i += kBlock) set[i] = kEmpty;
     }
     __syncthreads();
   }
@@ -442,8 +552,7 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   float qv[C][4];
   load_query<FPP_STORE_FP32, G, C>(Q + q * ldq, d, g, qv);
   const int32_t* sl = short_ids + (size_t)q * short_ld;
-  int Rp2 = 1;
-  while (Rp2 < R) Rp2 <<= 1;
+  const int Rp2 = sort_size((uint32_t)R);
   for (int r0 = 0; r0 < Rp2; r0 += 4 * RPI) {
     const int r = r0 + wave * RPI + sub;
     const int32_t id = r < R ? sl[r] : -1;
@@ -469,65 +578,43 @@ __global__ __launch_bounds__(256) void rerank_kernel(
   }
 }
 
-size_t score_lds_bytes(bool ldsbm) {
-  return kOffBitmap + (ldsbm ? (size_t)kLdsBitmapWords * 4 : 0);
-}
-
 template <int STORE, int G, int C>
-hipError_t launch_score_t(const ScoreParams& sp, int grid, bool ldsbm, hipStream_t s) {
-  const size_t lds = score_lds_bytes(ldsbm);
-  if (ldsbm) {
-    auto kern = score_kernel<STORE, G, C, true>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, sp);
-  } else {
-    auto kern = score_kernel<STORE, G, C, false>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, s, sp);
-  }
+hipError_t launch_score_t(const ScoreParams& sp, int grid, hipStream_t s) {
+  auto kern = score_kernel<STORE, G, C>;
+  const hipError_t e = hipFuncSetAttribute((const void*)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsBytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), kLdsBytes, s, sp);
   return hipGetLastError();
 }
 
 // (G, C) per store and chunk count: G = lanes per row (power of two), C = chunks per lane.
 template <int STORE>
-hipError_t dispatch_store(const ScoreParams& sp, int grid, bool ldsbm, hipStream_t s) {
+hipError_t dispatch_store(const ScoreParams& sp, int grid, hipStream_t s) {
   const int nc = sp.nchunks;
-  if (nc <= 8) return launch_score_t<STORE, 8, 1>(sp, grid, ldsbm, s);
-  if (nc <= 16) return launch_score_t<STORE, 16, 1>(sp, grid, ldsbm, s);
-  if (nc <= 32) return launch_score_t<STORE, 32, 1>(sp, grid, ldsbm, s);
-  if (nc <= 64) return launch_score_t<STORE, 64, 1>(sp, grid, ldsbm, s);
-  if (nc <= 128) return launch_score_t<STORE, 64, 2>(sp, grid, ldsbm, s);
-  if (nc <= 256) return launch_score_t<STORE, 64, 4>(sp, grid, ldsbm, s);
+  if (nc <= 8) return launch_score_t<STORE, 8, 1>(sp, grid, s);
+  if (nc <= 16) return launch_score_t<STORE, 16, 1>(sp, grid, s);
+  if (nc <= 32) return launch_score_t<STORE, 32, 1>(sp, grid, s);
+  if (nc <= 64) return launch_score_t<STORE, 64, 1>(sp, grid, s);
+  if (nc <= 128) return launch_score_t<STORE, 64, 2>(sp, grid, s);
+  if (nc <= 256) return launch_score_t<STORE, 64, 4>(sp, grid, s);
   return hipErrorInvalidValue;
 }
 
 }  // namespace
 
-bool score_bitmap_in_lds(const fpp_index* ix) {
-  if (ix->n > (int64_t)kLdsBitmapWords * 32) return false;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return false;
-  int lds_max = 0;
-  if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-    return false;
-  return (size_t)lds_max >= score_lds_bytes(true);
-}
-
 int score_grid_blocks(const fpp_index* ix) {
   (void)ix;
   int dev = 0, cus = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipGetDevice(&dev) != hipSuccess) return 256 * kBlocksPerCU;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 256;
-  return cus > 0 ? cus : 256;
+    return 256 * kBlocksPerCU;
+  return (cus > 0 ? cus : 256) * kBlocksPerCU;
 }
 
 hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) {
   if (a.m <= 0) return hipSuccess;
+  if (!a.gbitmap) return hipErrorInvalidValue;
   ScoreParams sp{};
   sp.offsets = ix->offsets;
   sp.ids = ix->ids;
@@ -551,26 +638,24 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.short_ld = a.short_ld;
   sp.lowp = a.store == FPP_STORE_FP32 ? 0 : 1;
   sp.R_opt = a.rerank_R;
-  const bool ldsbm = score_bitmap_in_lds(ix);
-  if (!ldsbm && !a.gbitmap) return hipErrorInvalidValue;
   const int grid = a.grid;
   switch (a.store) {
     case FPP_STORE_FP32:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->X);
       sp.ld_bytes = (int64_t)ix->ldx * 4;
       sp.nchunks = ix->ldx / 4;
-      return dispatch_store<FPP_STORE_FP32>(sp, grid, ldsbm, s);
+      return dispatch_store<FPP_STORE_FP32>(sp, grid, s);
     case FPP_STORE_BF16:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xbf16);
       sp.ld_bytes = (int64_t)ix->ld16 * 2;
       sp.nchunks = ix->ld16 / 8;
-      return dispatch_store<FPP_STORE_BF16>(sp, grid, ldsbm, s);
+      return dispatch_store<FPP_STORE_BF16>(sp, grid, s);
     case FPP_STORE_FP8:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xfp8);
       sp.ld_bytes = (int64_t)ix->ld8;
       sp.nchunks = ix->ld8 / 16;
       sp.scale = ix->fp8_scale;
-      return dispatch_store<FPP_STORE_FP8>(sp, grid, ldsbm, s);
+      return dispatch_store<FPP_STORE_FP8>(sp, grid, s);
     default:
       return hipErrorInvalidValue;
   }

@@ -139,6 +139,7 @@ struct Slot {
   float* d_Q = nullptr;           // [max_batch][d]
   int32_t* d_ids = nullptr;       // [max_batch * kMaxK]
   float* d_sc = nullptr;
+  uint32_t* d_gbm = nullptr;      // overflow dedup bitmaps of this slot's launches (kept zero)
   size_t ws_off = 0, ws_bytes = 0;
   std::vector<std::shared_ptr<Request>> reqs;
 };
@@ -169,14 +170,14 @@ namespace {
 
 size_t batch_bytes(const fpp_index* ix, const fpp_server_opts& o, int64_t m, int32_t kmax,
                    int32_t qpmax) {
-  return plan_layout(ix, m, qpmax, kmax, o.store, o.rerank_R, INT64_MAX).total;
+  return plan_layout(ix, m, qpmax, kmax, o.store, o.rerank_R, INT64_MAX, false).total;
 }
 
 void release_slot_buffers(Slot& s) {
   if (s.h_desc) (void)hipHostFree(s.h_desc);
   if (s.h_off) (void)hipHostFree(s.h_off);
   if (s.h_kq) (void)hipHostFree(s.h_kq);
-  void* d[] = {s.d_desc, s.d_off, s.d_kq, s.d_Q, s.d_ids, s.d_sc};
+  void* d[] = {s.d_desc, s.d_off, s.d_kq, s.d_Q, s.d_ids, s.d_sc, s.d_gbm};
   for (void* p : d)
     if (p) (void)hipFree(p);
   if (s.done) (void)hipEventDestroy(s.done);
@@ -222,9 +223,9 @@ int launch_batch(fpp_server* sv, Slot& s) {
   qs.R_opt = sv->opts.rerank_R;
   qs.ids_out = s.d_ids;
   qs.scores_out = s.d_sc;
-  const Layout ly = plan_layout(ix, m, qpmax, kmax, qs.store, qs.R_opt, INT64_MAX);
+  const Layout ly = plan_layout(ix, m, qpmax, kmax, qs.store, qs.R_opt, INT64_MAX, false);
+  qs.gbm_ext = s.d_gbm;
   unsigned char* ws = sv->pool_mem + s.ws_off;
-  if (ly.gbm) FPP_HIP(hipMemsetAsync(ws + ly.off_gbm, 0, ly.total - ly.off_gbm, st));
   FPP_TRY(run_queries(ix, qs, ly, ws, st));
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)m), dim3(256), 0, st, s.d_desc, s.d_off, s.d_kq,
                      m, s.d_ids, s.d_sc);
@@ -374,7 +375,9 @@ int fpp_server_create(const fpp_index* ix, const fpp_server_opts* opts, fpp_serv
         (e = hipMalloc((void**)&s.d_kq, sizeof(int32_t) * 2 * mb)) != hipSuccess ||
         (e = hipMalloc((void**)&s.d_Q, sizeof(float) * mb * ix->d)) != hipSuccess ||
         (e = hipMalloc((void**)&s.d_ids, sizeof(int32_t) * mb * kMaxK)) != hipSuccess ||
-        (e = hipMalloc((void**)&s.d_sc, sizeof(float) * mb * kMaxK)) != hipSuccess)
+        (e = hipMalloc((void**)&s.d_sc, sizeof(float) * mb * kMaxK)) != hipSuccess ||
+        (e = hipMalloc((void**)&s.d_gbm, overflow_bitmap_bytes(ix))) != hipSuccess ||
+        (e = hipMemset(s.d_gbm, 0, overflow_bitmap_bytes(ix))) != hipSuccess)
       return fail(hip_fail(e, "server slot allocation", __FILE__, __LINE__));
   }
   fpp_server* raw = sv.get();

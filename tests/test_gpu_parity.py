@@ -185,6 +185,21 @@ def test_query_fp32_matches_oracle(name, k):
     assert swaps <= max(2, w["Q"].shape[0] * k // 200), swaps
 
 
+@pytest.mark.parametrize("qp", [2000, 10 ** 6])
+def test_query_many_candidates_uses_bitmap_dedup(qp):
+    """More distinct candidates than the LDS id set holds: dedup moves to the device bitmap."""
+    w, oi, h, Xd, Qd = built("l2_clustered")
+    ids, sc, st = F().fpp_query(h, Qd, 100, qp, stats=True)
+    oids, osc, ost = O.query(oi, w["Q"], 100, qp)
+    st = st.cpu().numpy()
+    np.testing.assert_array_equal(st, ost)
+    assert st[:, 2].max() > 3072
+    assert check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 100, 128) <= 20
+    # a second call reuses the (cleared) bitmaps
+    ids2, sc2 = F().fpp_query(h, Qd, 100, qp)
+    assert torch.equal(ids, ids2) and torch.equal(sc, sc2)
+
+
 def test_query_c1_published_qprobes():
     """The small workload as specified: k = 10, 4 probes per table (40 in total), and the
     literal total of 4."""
