@@ -25,107 +25,115 @@ __device__ __forceinline__ float flip(float v, uint32_t mask) {
 }
 
 // ------------------------------------------------------------------------------------------
-// Query side. One wavefront per (vector, function), everything in registers: lane x holds the
-// elements j = e * 64 + x (e < E = P / 64; for P < 64 lanes x < P hold one element). Butterfly
-// stages h < 64 pair lane x with lane x ^ h (the lower lane adds, the upper subtracts), stages
-// h >= 64 pair register e with e ^ (h / 64) inside the lane, in the order h = 1, 2, ..., P/2.
+// Query side, everything in registers. An item (vector, function) spans LPI = P / E lanes of a
+// wavefront; lane x of the item holds the E consecutive elements j = x * E + e. Butterfly stages
+// h < E pair register e with e ^ h inside the lane; stages h >= E pair lane x with x ^ (h / E)
+// (the lower lane adds, the upper subtracts); stages run in the order h = 1, 2, ..., P/2.
 // The D keys (|y_i| bits << 32 | (0xffff - i) << 1 | sign) are then bitonic-sorted descending in
 // the same layout, which orders the list by (|y| desc, i asc) and carries the code bit.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m, int width) {
+  const uint32_t lo = __shfl_xor((uint32_t)v, m, width), hi = __shfl_xor((uint32_t)(v >> 32), m, width);
   return ((uint64_t)hi << 32) | lo;
 }
+
+template <int P>
+struct QLayout {
+  static constexpr int E = P < 8 ? P : (P / 64 > 8 ? P / 64 : 8);   // elements per lane
+  static constexpr int LPI = P / E;                                 // lanes per item
+  static constexpr int IPW = 64 / LPI;                              // items per wavefront
+};
 
 template <int P>
 __global__ __launch_bounds__(256) void hash_query_kernel(
     const float* __restrict__ V, int64_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
     int LF, int D, float* __restrict__ la, uint16_t* __restrict__ lc) {
-  constexpr int E = P >= 64 ? P / 64 : 1;
-  constexpr int XS = P >= 64 ? 64 : P;   // lanes that hold elements
+  constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI, IPW = QLayout<P>::IPW;
   const int lane = threadIdx.x & 63;
-  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (item >= m * LF) return;   // whole wavefront
-  const int64_t q = item / LF;
-  const int tf = (int)(item - q * LF);
-  const bool on = lane < XS;
+  const int li = lane % LPI;
+  const int64_t items = m * LF;
+  const int64_t item = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * IPW + lane / LPI;
+  if (((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * IPW >= items) return;   // whole wavefront
+  const bool valid = item < items;   // uniform over the item's lanes
+  const int64_t it = valid ? item : 0;
+  const int64_t q = it / LF;
+  const int tf = (int)(it - q * LF);
+  const int j0 = li * E;
 
   float v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = e * 64 + lane;
-    v[e] = (on && j < d) ? V[q * ldv + j] : 0.0f;
-  }
-  const uint32_t* sm = sign_mask + (size_t)tf * 3 * P;
+  for (int e = 0; e < E; ++e) v[e] = (j0 + e < d) ? V[q * ldv + j0 + e] : 0.0f;
+  const uint32_t* sm = sign_mask + (size_t)tf * 3 * P + j0;
+#pragma unroll
   for (int r = 0; r < 3; ++r) {
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (on) v[e] = flip(v[e], sm[r * P + e * 64 + lane]);
+    for (int e = 0; e < E; ++e) v[e] = flip(v[e], sm[r * P + e]);
 #pragma unroll
-    for (int h = 1; h < XS; h <<= 1) {
-      const bool upper = (lane & h) != 0;
+    for (int h = 1; h < E; h <<= 1) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const float w = __shfl_xor(v[e], h);
-        v[e] = upper ? w - v[e] : v[e] + w;
+        if ((e & h) == 0) {
+          const float a = v[e], b = v[e + h];
+          v[e] = a + b;
+          v[e + h] = a - b;
+        }
       }
     }
 #pragma unroll
-    for (int hh = 1; hh < E; hh <<= 1) {
+    for (int hl = 1; hl < LPI; hl <<= 1) {
+      const bool upper = (li & hl) != 0;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        if ((e & hh) == 0) {
-          const float a = v[e], b = v[e + hh];
-          v[e] = a + b;
-          v[e + hh] = a - b;
-        }
+        const float w = __shfl_xor(v[e], hl, LPI);
+        v[e] = upper ? w - v[e] : v[e] + w;
       }
     }
   }
   uint64_t key[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int i = e * 64 + lane;
+    const int i = j0 + e;
     const uint32_t neg = v[e] >= 0.0f ? 0u : 1u;
-    key[e] = (on && i < D) ? ((uint64_t)__float_as_uint(fabsf(v[e])) << 32) |
-                                 ((uint32_t)(0xffff - i) << 1) | neg
-                           : 0ull;
+    key[e] = i < D ? ((uint64_t)__float_as_uint(fabsf(v[e])) << 32) | ((uint32_t)(0xffff - i) << 1) | neg
+                   : 0ull;
   }
-  // bitonic sort (descending) of the first D keys, D a power of two
-  for (int k = 2; k <= D; k <<= 1) {
-    for (int j = k >> 1; j > 0; j >>= 1) {
-      if (j < 64) {
+  // bitonic sort (descending) of the first D keys (D a power of two <= P)
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const int i = e * 64 + lane;
-          const uint64_t o = shfl_xor_u64(key[e], j);
-          const bool lower = (i & j) == 0, desc = (i & k) == 0;
-          const uint64_t mx = key[e] > o ? key[e] : o, mn = key[e] > o ? o : key[e];
-          key[e] = (lower == desc) ? mx : mn;
-        }
-      } else {
-        const int jj = j >> 6;
+  for (int k = 2; k <= P; k <<= 1) {
+    if (k <= D) {
+      // direction of element j0 + e in stage k: compile-time for k < E, lane-uniform for k >= E
+      const bool desc_lane = (j0 & k) == 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          if ((e & jj) == 0 && (e | jj) < E) {
-            const int i = e * 64 + lane;
-            const bool desc = (i & k) == 0;
-            const uint64_t a = key[e], b = key[e | jj];
-            if (desc ? (a < b) : (a > b)) {
-              key[e] = b;
-              key[e | jj] = a;
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        if (j < E) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if ((e & j) == 0) {
+              const bool desc = k < E ? ((e & k) == 0) : desc_lane;
+              const uint64_t a = key[e], b = key[e | j];
+              const bool sw = desc ? (a < b) : (b < a);
+              key[e] = sw ? b : a;
+              key[e | j] = sw ? a : b;
             }
+          }
+        } else {
+          const bool keep_max = ((li & (j / E)) == 0) == desc_lane;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const uint64_t o = shfl_xor_u64(key[e], j / E, LPI);
+            key[e] = ((key[e] > o) == keep_max) ? key[e] : o;
           }
         }
       }
     }
   }
+  if (!valid) return;
   float* ola = la + (size_t)item * D;
   uint16_t* olc = lc + (size_t)item * D;
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    const int p = e * 64 + lane;
-    if (on && p < D) {
+    const int p = j0 + e;
+    if (p < D) {
       const uint64_t kk = key[e];
       const int idx = 0xffff - (int)(((uint32_t)kk & 0x1ffffu) >> 1);
       ola[p] = __uint_as_float((uint32_t)(kk >> 32));
@@ -154,12 +162,13 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
   if (m <= 0) return hipSuccess;
   const int LF = ix->L * ix->l;
   const int64_t items = m * LF;
-  const dim3 grid((unsigned)((items + 3) / 4)), block(256);
 #define FPP_HQ(PP)                                                                             \
-  case PP:                                                                                     \
-    hipLaunchKernelGGL(hash_query_kernel<PP>, grid, block, 0, s, V, m, ldv, ix->d, ix->sign_mask, \
-                       LF, ix->D, la, lc);                                                     \
-    break;
+  case PP: {                                                                                   \
+    const int64_t waves = (items + QLayout<PP>::IPW - 1) / QLayout<PP>::IPW;                   \
+    hipLaunchKernelGGL(hash_query_kernel<PP>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, \
+                       V, m, ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc);                    \
+    break;                                                                                     \
+  }
   switch (ix->P) {
     FPP_HQ(2) FPP_HQ(4) FPP_HQ(8) FPP_HQ(16) FPP_HQ(32) FPP_HQ(64) FPP_HQ(128) FPP_HQ(256)
     FPP_HQ(512) FPP_HQ(1024) FPP_HQ(2048) FPP_HQ(4096)
