@@ -62,6 +62,22 @@ def algorithmic_bytes(stats: np.ndarray, d: int, store: str, k: int, R: int) -> 
     return float(8 * stats[:, 0].sum() + 4 * stats[:, 1].sum() + row * stats[:, 2].sum() + out * m)
 
 
+def traffic_per_call(dom):
+    """HBM bytes per call of the gather kernel measured with rocprofv3 counters (profiles/), or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "score_kernel_traffic.json")
+    src = os.path.join(ROOT, "paper_2206_01382_amd", "csrc", "score.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except Exception:
+        return None
+    if rec.get("score_hip_sha256") != digest:
+        return None
+    return rec.get("hbm_bytes_per_call")
+
+
 def timed_steps(torch, F, h, Qd, k, qp, store, steps, warmup):
     stage = np.zeros(4)
     tot = np.zeros(4)
@@ -178,8 +194,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serving-queries", type=int, default=60_000)
-    ap.add_argument("--traffic-gbs", type=float, default=None,
-                    help="HBM traffic of the gather kernel from rocprofv3 counters (GB per call)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 1 GiB device-to-device copy (scale for rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus N>1 is not supported"}), flush=True)
@@ -192,6 +208,14 @@ def main():
 
     F.lib()
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del src, dst
     t = time.perf_counter()
     w = synthdata.workload("c2_cluster_1m_d128")
     log(f"data {w.X.shape} queries {w.Q.shape} in {time.perf_counter() - t:.1f}s")
@@ -277,7 +301,7 @@ def main():
     dom = head
     roof = {"bound": "hbm", "achieved": round(dom["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(dom["gbs"] / HBM_PEAK_GBS, 4),
-            "traffic": args.traffic_gbs,
+            "traffic": traffic_per_call(dom),
             "kernel": "score_kernel (candidate gather + dedup + score + top-R), BF16 store",
             "algorithmic_bytes_per_call": dom["bytes"], "kernel_ms_per_call": dom["stage_ms"][2]}
     ser = serving.get("0.8") or {}

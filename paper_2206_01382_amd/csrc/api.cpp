@@ -190,7 +190,7 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   // tables per pass from free memory (at most a quarter of it, at most 4 GiB of scratch)
   size_t free_b = 0, total_b = 0;
   FPP_HIP(hipMemGetInfo(&free_b, &total_b));
-  const int64_t per_tab_scratch = nK * 16 + NB * 12 + (NB + 1) * 4 + 64;
+  const int64_t per_tab_scratch = nK * 16 + NB * 20 + (NB + 1) * 4 + 64;
   const int64_t budget = std::min<int64_t>((int64_t)free_b / 4, (int64_t)4 << 30);
   int Tc = o.tables_per_pass > 0 ? o.tables_per_pass : (int)std::max<int64_t>(1, budget / per_tab_scratch);
   Tc = std::min(Tc, L);
@@ -207,6 +207,8 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
     FPP_TRY(sc.get(&bs.fill, (size_t)Tc * NB));
     FPP_TRY(sc.get(&bs.meta, (size_t)(2 + Tc)));
     FPP_TRY(sc.get(&bs.tbase, (size_t)(L + 1)));
+    FPP_TRY(sc.get(&bs.large, (size_t)Tc * NB));
+    FPP_TRY(sc.get(&bs.n_large, (size_t)1));
     FPP_HIP(hipMemsetAsync(bs.meta, 0, sizeof(uint64_t) * (2 + Tc), s));
     for (int t0 = 0; t0 < L; t0 += Tc) {
       const int tc = std::min(Tc, L - t0);

@@ -102,6 +102,8 @@ struct BuildScratch {
   uint32_t* fill;         // [Tc][NB]
   uint64_t* meta;         // [2 + Tc]: running base, max bucket, per-table sizes
   uint64_t* tbase;        // [L + 1]: start of each table in the ids array
+  uint64_t* large;        // [Tc][NB]: (table in chunk << 32 | bucket) of buckets > 64 records
+  uint32_t* n_large;      // [1]
 };
 hipError_t launch_build_tables(const fpp_index* ix, int t0, int Tc, const BuildScratch& b,
                                hipStream_t s);
@@ -181,7 +183,7 @@ int check_store(const fpp_index* ix, int32_t store);
 // Scratch layout for m queries; queries are processed in chunks so that one chunk's lists and
 // probes stay within `budget` bytes.
 Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max, int32_t store,
-                   int32_t R_opt, int64_t budget = (int64_t)1 << 30, bool gbm_in_scratch = true);
+                   int32_t R_opt, int64_t budget = (int64_t)4 << 30, bool gbm_in_scratch = true);
 // Bytes of the overflow bitmaps of one score launch.
 size_t overflow_bitmap_bytes(const fpp_index* ix);
 // Runs hash -> probe selection -> score (-> rerank) over [0, qs.m) with device scratch `ws`

@@ -305,7 +305,8 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
   constexpr int RPI = 64 / G;              // rows per wave instruction
   constexpr int RPW = U * RPI;             // rows per wave pass
   constexpr int RPB = RPW * kWaves;        // rows per block pass
-  static_assert(RPB <= kCandCap / 4, "candidate buffer too small");
+  constexpr int PPC = RPB >= kCandCap / 2 ? 1 : (kCandCap / 2) / RPB;   // passes per block sync
+  static_assert(PPC * RPB <= kCandCap / 2, "candidate buffer too small");
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* cand = reinterpret_cast<uint64_t*>(smem + kOffCand);
@@ -352,72 +353,103 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       __syncthreads();
     };
 
-    // ---- B: scoring of the queued ids
-    auto score_queue = [&]() {
+    // ---- B: scoring of the queued ids. Each wave walks its rows in passes of RPW rows; the
+    // loads of the next pass are issued before the current pass is folded (two register sets).
+    // The block synchronises every PPC passes, when the candidate buffer may need compaction.
+    auto load_pass = [&](uint32_t rbase, uint32_t rows, int32_t (&rid)[U], uint4 (&w)[U][C]) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t row = rbase + u * RPI + sub;
+        rid[u] = row < rows ? (int32_t)queue[row] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const int ci = c * G + g;
+          if (rid[u] >= 0 && ci < p.nchunks)
+            w[u][c] = *reinterpret_cast<const uint4*>(p.Xs + (size_t)rid[u] * p.ld_bytes +
+                                                      (size_t)ci * 16);
+          else
+            w[u][c] = make_uint4(0u, 0u, 0u, 0u);
+        }
+      }
+    };
+    auto fold_pass = [&](const int32_t (&rid)[U], const uint4 (&w)[U][C], uint64_t thr) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        float part = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c) part = fold_chunk<STORE>(part, qv[c], w[u][c]);
+        float s = tree_sum<G>(part);
+        if constexpr (STORE == FPP_STORE_FP8) {
+          if (rid[u] >= 0) s = s * p.scale[rid[u]];
+        }
+        if (g == 0 && rid[u] >= 0) {
+          const uint64_t key = make_key(s, rid[u]);
+          if (key > thr) cand[atomicAdd(&st->ccount, 1u)] = key;
+        }
+      }
+    };
+    // flush the queue through the scoring passes; `last` also leaves the candidates sorted
+    auto score_queue = [&](bool last) {
       const uint32_t rows = st->qcount;
-      for (uint32_t pb = 0; pb < rows; pb += RPB) {
-        const uint32_t base = pb + wave * RPW;
-        int32_t rid[U];
-        uint4 w[U][C];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t row = base + u * RPI + sub;
-          rid[u] = row < rows ? (int32_t)queue[row] : -1;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) {
-            const int ci = c * G + g;
-            if (rid[u] >= 0 && ci < p.nchunks)
-              w[u][c] = *reinterpret_cast<const uint4*>(p.Xs + (size_t)rid[u] * p.ld_bytes +
-                                                        (size_t)ci * 16);
-            else
-              w[u][c] = make_uint4(0u, 0u, 0u, 0u);
-          }
-        }
+      for (uint32_t sb = 0; sb < rows || (last && sb == 0); sb += PPC * RPB) {
         const uint64_t thr = st->thr;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          float part = 0.0f;
-#pragma unroll
-          for (int c = 0; c < C; ++c) part = fold_chunk<STORE>(part, qv[c], w[u][c]);
-          float s = tree_sum<G>(part);
-          if constexpr (STORE == FPP_STORE_FP8) {
-            if (rid[u] >= 0) s = s * p.scale[rid[u]];
-          }
-          if (g == 0 && rid[u] >= 0) {
-            const uint64_t key = make_key(s, rid[u]);
-            if (key > thr) cand[atomicAdd(&st->ccount, 1u)] = key;
+        int32_t ra[U], rb[U];
+        uint4 wa[U][C], wb[U][C];
+        load_pass(sb + wave * RPW, rows, ra, wa);
+#pragma unroll 1
+        for (int ps = 0; ps < PPC; ps += 2) {
+          // even pass folds set a while set b loads; odd pass the other way round
+          if (ps + 1 < PPC) load_pass(sb + (ps + 1) * RPB + wave * RPW, rows, rb, wb);
+          fold_pass(ra, wa, thr);
+          if (ps + 1 < PPC) {
+            if (ps + 2 < PPC) load_pass(sb + (ps + 2) * RPB + wave * RPW, rows, ra, wa);
+            fold_pass(rb, wb, thr);
           }
         }
         __syncthreads();
-        if (st->ccount > (uint32_t)(kCandCap - RPB)) compact();
+        const bool fin = last && sb + PPC * RPB >= rows;
+        if (fin || st->ccount > (uint32_t)(kCandCap - PPC * RPB)) compact();
       }
       if (tid == 0) st->qcount = 0;
       __syncthreads();
     };
 
-    // ---- A: gather + dedup
+    // ---- A: gather + dedup, flushing the queue into B whenever it fills
     const int32_t np = p.nprobe[q];
     const uint32_t* pr = p.probes + (size_t)q * p.qcap;
     uint64_t entries = 0;
-    for (int32_t pc = 0; pc < np; pc += kProbeChunk) {
-      const int npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
-      uint32_t beg = 0, len = 0;
-      if (tid < npc) {
-        const uint32_t gb = pr[pc + tid];
-        beg = p.offsets[gb];
-        len = p.offsets[gb + 1] - beg;
-      }
-      uint32_t ec;
-      const uint32_t pre = block_excl_scan(len, ec, wsum);
-      s_beg[tid] = beg;
-      s_pre[tid] = pre;
-      if (tid == 0) s_pre[kProbeChunk] = ec;
-      __syncthreads();
-      entries += ec;
-      for (uint32_t e0 = 0; e0 < ec; e0 += kRound) {
+    int32_t pc = 0;      // next probe chunk
+    int npc = 0;         // probes in the current chunk
+    uint32_t ec = 0;     // entries of the current chunk
+    uint32_t e0 = 0;     // next entry of the current chunk
+    for (;;) {
+      bool exhausted = false;
+      while (st->qcount < (uint32_t)kQueueFlush) {
+        if (e0 >= ec) {
+          if (pc >= np) {
+            exhausted = true;
+            break;
+          }
+          npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
+          uint32_t beg = 0, len = 0;
+          if (tid < npc) {
+            const uint32_t gb = pr[pc + tid];
+            beg = p.offsets[gb];
+            len = p.offsets[gb + 1] - beg;
+          }
+          const uint32_t pre = block_excl_scan(len, ec, wsum);
+          s_beg[tid] = beg;
+          s_pre[tid] = pre;
+          if (tid == 0) s_pre[kProbeChunk] = ec;
+          __syncthreads();
+          entries += ec;
+          pc += kProbeChunk;
+          e0 = 0;
+          continue;
+        }
         const bool ovf = st->overflow != 0;
         // four consecutive entries per thread: one search, then a linear walk over the probes
         const uint32_t e = e0 + (uint32_t)tid * kEPT;
@@ -440,6 +472,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
             }
           }
         }
+        e0 += kRound;
         uint32_t fresh = 0;   // bit u: entry u is a first occurrence
 #pragma unroll
         for (int u = 0; u < kEPT; ++u) {
@@ -468,7 +501,6 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         for (int u = 0; u < kEPT; ++u)
           if (fresh & (1u << u)) queue[pos++] = (uint32_t)idv[u];
         __syncthreads();
-        if (st->qcount >= (uint32_t)kQueueFlush) score_queue();
         if (!st->overflow && st->uniq > (uint32_t)kSetLimit) {
           // move the set into the device bitmap; later entries are tested there
           for (int i = tid; i < kSetSlots; i += kBlock) {
@@ -484,13 +516,12 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
           __syncthreads();
         }
       }
-      __syncthreads();
+      score_queue(exhausted);
+      if (exhausted) break;
     }
-    if (st->qcount) score_queue();
 
-    // ---- C: final order and output
+    // ---- C: output (the candidates are sorted)
     {
-      compact();
       const uint32_t c0 = st->ccount;
       if (!p.lowp) {
         const int64_t o = p.out_off ? p.out_off[q] : q * (int64_t)k;

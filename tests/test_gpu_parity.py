@@ -317,6 +317,26 @@ def test_duplicate_points_and_zero_query():
         F().fpp_free_index(h)
 
 
+def test_huge_buckets_beyond_lds_sort():
+    """Buckets of more than 8192 records (many equal points) are ranked by counting."""
+    rng = np.random.default_rng(5)
+    base = rng.standard_normal((3, 16))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    X = base[rng.integers(0, 3, size=30_000)].astype(np.float32)
+    X[::7] += np.float32(1e-3)          # some distinct keys among the equal ones
+    for l, D, ip in ((1, 8, 1), (2, 4, 2)):
+        Xd, h = _small_index(X, 2, D, 0.4, ip, l)
+        try:
+            oi = O.build_index(X, 2, D, 0.4, ip, 3, l=l)
+            assert max(int(np.max(np.diff(o))) for o in oi.offsets) > 2000
+            for t in range(2):
+                off, ids = F().fpp_debug_export_table(h, t)
+                np.testing.assert_array_equal(off, oi.offsets[t])
+                np.testing.assert_array_equal(ids, oi.ids[t])
+        finally:
+            F().fpp_free_index(h)
+
+
 def test_tiny_d1_D2_L1():
     X = np.where(np.arange(50) % 2 == 0, 1.0, -1.0).astype(np.float32)[:, None]
     Q = np.array([[1.0], [-1.0]], np.float32)

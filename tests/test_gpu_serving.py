@@ -1,0 +1,135 @@
+"""Serving loop (continuous batching) through the C ABI: every request's result equals the same
+query run alone, admission by scratch bytes neither loses nor duplicates requests, requests larger
+than the pool are rejected, and timestamps are consistent."""
+import time
+
+import numpy as np
+import pytest
+
+import synthdata
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def env():
+    import paper_2206_01382_amd as F
+    assert torch.cuda.is_available()
+    X, Q = synthdata.clustered_sphere(30_000, 64, 300, 40, 0.3, seed=11)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    h = F.fpp_build_index(Xd, 8, 32, 0.3, 3, 77, l=2, stores=("bf16",))
+    yield F, h, Xd, Qd
+    F.fpp_free_index(h)
+
+
+def _requests(rng, m_total, n_req, ks, qps):
+    reqs = []
+    row = 0
+    for _ in range(n_req):
+        m = int(rng.integers(1, 17))
+        if row + m > m_total:
+            row = 0
+        reqs.append((row, m, int(rng.choice(ks)), int(rng.choice(qps))))
+        row += m
+    return reqs
+
+
+def _run(F, sv, Qd, reqs, kmax, pace_s=0.0):
+    outs = []
+    tickets = []
+    for (row, m, k, qp) in reqs:
+        ids = torch.full((m, k), -7, dtype=torch.int32, device="cuda")
+        sc = torch.full((m, k), 7.0, dtype=torch.float32, device="cuda")
+        q = Qd[row:row + m]
+        tickets.append(F.fpp_server_submit(sv, q.data_ptr(), m, k, qp, ids.data_ptr(), sc.data_ptr()))
+        outs.append((ids, sc))
+        if pace_s:
+            time.sleep(pace_s)
+    stamps = [F.fpp_server_wait(sv, t, 60_000) for t in tickets]
+    return outs, stamps, tickets
+
+
+@pytest.mark.parametrize("store", ["fp32", "bf16"])
+def test_results_alone_equal_results_in_the_mix(env, store):
+    F, h, Xd, Qd = env
+    rng = np.random.default_rng(1)
+    reqs = _requests(rng, Qd.shape[0], 120, (1, 10, 100), (8, 40, 200))
+    sv = F.fpp_server_create(h, scratch_bytes=256 << 20, n_streams=3, max_batch=64, store=store)
+    try:
+        outs, stamps, _ = _run(F, sv, Qd, reqs, 100)
+        st = F.fpp_server_get_stats(sv)
+    finally:
+        F.fpp_server_destroy(sv)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["batches"] < len(reqs)              # requests were batched together
+    for (row, m, k, qp), (ids, sc), (status, ts, td) in zip(reqs, outs, stamps):
+        assert status == 0 and 0 < ts <= td
+        ri, rs = F.fpp_query(h, Qd[row:row + m].contiguous(), k, qp, store=store)
+        assert torch.equal(ids, ri) and torch.equal(sc, rs)
+
+
+def test_small_pool_admission_and_oversized_requests(env):
+    F, h, Xd, Qd = env
+    pool = 64 << 10      # a few small batches fit; a 16-query request with all probes does not
+    sv = F.fpp_server_create(h, scratch_bytes=pool, n_streams=4, max_batch=16)
+    try:
+        rng = np.random.default_rng(2)
+        reqs = [(int(r), int(m), 10, 40) for r, m in zip(rng.integers(0, Qd.shape[0] - 4, size=60),
+                                                         rng.integers(1, 5, size=60))]
+        outs, stamps, tickets = _run(F, sv, Qd, reqs, 10)
+        st = F.fpp_server_get_stats(sv)
+        assert st["completed"] == 60 and st["failed"] == 0
+        assert 0 < st["scratch_high_water"] <= pool
+        assert len(set(tickets)) == 60
+        for (row, m, k, qp), (ids, sc) in zip(reqs, outs):
+            ri, rs = F.fpp_query(h, Qd[row:row + m].contiguous(), k, qp)
+            assert torch.equal(ids, ri) and torch.equal(sc, rs)
+        ids = torch.empty((17, 10), dtype=torch.int32, device="cuda")
+        sc = torch.empty((17, 10), dtype=torch.float32, device="cuda")
+        with pytest.raises(F.FppError) as e:    # needs more scratch than the pool holds
+            F.fpp_server_submit(sv, Qd.data_ptr(), 16, 10, 10 ** 6, ids.data_ptr(), sc.data_ptr())
+        assert e.value.code == F.FPP_ECAPACITY
+        with pytest.raises(F.FppError) as e:    # more queries than one launch packs
+            F.fpp_server_submit(sv, Qd.data_ptr(), 17, 10, 40, ids.data_ptr(), sc.data_ptr())
+        assert e.value.code == F.FPP_ECAPACITY
+        t = F.fpp_server_submit(sv, Qd.data_ptr(), 4, 10, 40, ids.data_ptr(), sc.data_ptr())
+        assert F.fpp_server_wait(sv, t, 60_000)[0] == 0   # the loop keeps serving
+    finally:
+        F.fpp_server_destroy(sv)
+
+
+def test_poll_reports_a_completed_ticket_once(env):
+    F, h, Xd, Qd = env
+    sv = F.fpp_server_create(h, scratch_bytes=64 << 20, n_streams=2, max_batch=16)
+    try:
+        ids = torch.empty((2, 10), dtype=torch.int32, device="cuda")
+        sc = torch.empty((2, 10), dtype=torch.float32, device="cuda")
+        t = F.fpp_server_submit(sv, Qd.data_ptr(), 2, 10, 40, ids.data_ptr(), sc.data_ptr())
+        for _ in range(2000):
+            st, ts, td = F.fpp_server_poll(sv, t)
+            if st != 1:
+                break
+            time.sleep(0.001)
+        assert st == 0 and td >= ts > 0
+        with pytest.raises(F.FppError):
+            F.fpp_server_poll(sv, t)
+    finally:
+        F.fpp_server_destroy(sv)
+
+
+def test_overlapping_batches_on_several_streams(env):
+    F, h, Xd, Qd = env
+    sv = F.fpp_server_create(h, scratch_bytes=1 << 30, n_streams=4, max_batch=32)
+    try:
+        rng = np.random.default_rng(3)
+        reqs = _requests(rng, Qd.shape[0], 400, (10,), (40, 400))
+        outs, stamps, _ = _run(F, sv, Qd, reqs, 10)
+        st = F.fpp_server_get_stats(sv)
+    finally:
+        F.fpp_server_destroy(sv)
+    assert st["completed"] == 400 and st["max_inflight_batches"] >= 2
+    for (row, m, k, qp), (ids, sc) in zip(reqs[::20], outs[::20]):
+        ri, rs = F.fpp_query(h, Qd[row:row + m].contiguous(), k, qp)
+        assert torch.equal(ids, ri) and torch.equal(sc, rs)
