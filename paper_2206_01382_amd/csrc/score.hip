@@ -133,6 +133,52 @@ __device__ __forceinline__ void load_query(const float* qrow, int d, int g,
     }
 }
 
+// Reduce U rows at once over a G-lane group (U, G powers of two). Levels run at distances G/2,
+// G/4, ..., 1 like tree_sum, so every row is summed over exactly the same pairs in the same order
+// (float addition is commutative), but while a lane still holds several rows it sends half of
+// them to its partner and keeps the other half: 8 rows over 32 lanes take 9 shuffles instead of
+// 40. Afterwards lane g holds the total of row reduced_row<G, U>(g) in part[0].
+template <int G, int U>
+__device__ __forceinline__ void reduce_rows(float (&part)[U], int g) {
+  int n = U;
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    if (n > 1) {
+      const bool upper = (g & o) != 0;
+#pragma unroll
+      for (int i = 0; i < U / 2; ++i) {
+        if (i < n / 2) {
+          const float send = upper ? part[i] : part[i + n / 2];
+          const float keep = upper ? part[i + n / 2] : part[i];
+          part[i] = keep + __shfl_xor(send, o, G);
+        }
+      }
+      n >>= 1;
+    } else {
+      part[0] += __shfl_xor(part[0], o, G);
+    }
+  }
+}
+
+// Row whose total lane g holds after reduce_rows, and whether g reports it (one lane per row).
+template <int G, int U>
+__device__ __forceinline__ int reduced_row(int g) {
+  int row = 0, n = U;
+#pragma unroll
+  for (int o = G / 2; o > 0 && n > 1; o >>= 1) {
+    n >>= 1;
+    if (g & o) row += n;
+  }
+  return row;
+}
+template <int G, int U>
+__device__ __forceinline__ bool reports_row(int g) {
+  // the transposing levels use the top log2(U) bits of g; the butterfly levels below them leave
+  // equal totals in lanes that differ only in the low bits, of which the one with zeros reports
+  static_assert(U <= G, "more rows than lanes per group");
+  return (g & (G / U - 1)) == 0;
+}
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
   const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
   return ((uint64_t)hi << 32) | lo;
@@ -305,8 +351,8 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
   constexpr int RPI = 64 / G;              // rows per wave instruction
   constexpr int RPW = U * RPI;             // rows per wave pass
   constexpr int RPB = RPW * kWaves;        // rows per block pass
-  constexpr int PPC = RPB >= kCandCap / 2 ? 1 : (kCandCap / 2) / RPB;   // passes per block sync
-  static_assert(PPC * RPB <= kCandCap / 2, "candidate buffer too small");
+  constexpr int PPC = RPB >= 128 ? 1 : 128 / RPB;   // passes between block syncs (<= 128 rows)
+  static_assert(PPC * RPB <= kCandCap / 4, "candidate buffer too small");
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* cand = reinterpret_cast<uint64_t*>(smem + kOffCand);
@@ -376,21 +422,34 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       }
     };
     auto fold_pass = [&](const int32_t (&rid)[U], const uint4 (&w)[U][C], uint64_t thr) {
+      float part[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        float part = 0.0f;
+        part[u] = 0.0f;
 #pragma unroll
-        for (int c = 0; c < C; ++c) part = fold_chunk<STORE>(part, qv[c], w[u][c]);
-        float s = tree_sum<G>(part);
-        if constexpr (STORE == FPP_STORE_FP8) {
-          if (rid[u] >= 0) s = s * p.scale[rid[u]];
-        }
-        if (g == 0 && rid[u] >= 0) {
-          const uint64_t key = make_key(s, rid[u]);
-          if (key > thr) cand[atomicAdd(&st->ccount, 1u)] = key;
-        }
+        for (int c = 0; c < C; ++c) part[u] = fold_chunk<STORE>(part[u], qv[c], w[u][c]);
+      }
+      reduce_rows<G, U>(part, g);
+      const int row = reduced_row<G, U>(g);
+      int32_t myid = rid[0];
+#pragma unroll
+      for (int u = 1; u < U; ++u)
+        if (row == u) myid = rid[u];
+      float s = part[0];
+      if constexpr (STORE == FPP_STORE_FP8) {
+        if (myid >= 0) s = s * p.scale[myid];
+      }
+      const uint64_t key = make_key(s, myid);
+      const bool pass = reports_row<G, U>(g) && myid >= 0 && key > thr;
+      const uint64_t mask = __ballot(pass);
+      if (mask) {
+        uint32_t basepos = 0;
+        if (lane == 0) basepos = atomicAdd(&st->ccount, (uint32_t)__popcll(mask));
+        basepos = __shfl(basepos, 0);
+        if (pass) cand[basepos + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = key;
       }
     };
+
     // flush the queue through the scoring passes; `last` also leaves the candidates sorted
     auto score_queue = [&](bool last) {
       const uint32_t rows = st->qcount;
@@ -411,7 +470,11 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         }
         __syncthreads();
         const bool fin = last && sb + PPC * RPB >= rows;
-        if (fin || st->ccount > (uint32_t)(kCandCap - PPC * RPB)) compact();
+        // compact once the buffer holds more than max(2 kk, 128) entries: small sorts, and the
+        // threshold rises early so that most later rows are rejected without a store
+        uint32_t trig = (uint32_t)(2 * kk > 128 ? 2 * kk : 128);
+        if (trig > (uint32_t)(kCandCap - PPC * RPB)) trig = (uint32_t)(kCandCap - PPC * RPB);
+        if (fin || st->ccount > trig) compact();
       }
       if (tid == 0) st->qcount = 0;
       __syncthreads();
