@@ -144,6 +144,7 @@ hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m
                          int k_uniform, int R_opt, const int64_t* out_off, int32_t* ids_out,
                          float* scores_out, hipStream_t s);
 int score_grid_blocks(const fpp_index* ix);
+int64_t overflow_bitmap_words(const fpp_index* ix);   // per score workgroup
 int32_t short_list_len(int32_t R_opt, int32_t k);
 
 // ----------------------------------------------------------------------------------------------

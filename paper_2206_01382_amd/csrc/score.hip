@@ -138,24 +138,21 @@ __device__ __forceinline__ void load_query(const float* qrow, int d, int g,
 // (float addition is commutative), but while a lane still holds several rows it sends half of
 // them to its partner and keeps the other half: 8 rows over 32 lanes take 9 shuffles instead of
 // 40. Afterwards lane g holds the total of row reduced_row<G, U>(g) in part[0].
-template <int G, int U>
+template <int G, int U, int O = G / 2, int N = U>
 __device__ __forceinline__ void reduce_rows(float (&part)[U], int g) {
-  int n = U;
+  if constexpr (O > 0) {
+    if constexpr (N > 1) {
+      const bool upper = (g & O) != 0;
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-    if (n > 1) {
-      const bool upper = (g & o) != 0;
-#pragma unroll
-      for (int i = 0; i < U / 2; ++i) {
-        if (i < n / 2) {
-          const float send = upper ? part[i] : part[i + n / 2];
-          const float keep = upper ? part[i + n / 2] : part[i];
-          part[i] = keep + __shfl_xor(send, o, G);
-        }
+      for (int i = 0; i < N / 2; ++i) {
+        const float send = upper ? part[i] : part[i + N / 2];
+        const float keep = upper ? part[i + N / 2] : part[i];
+        part[i] = keep + __shfl_xor(send, O, G);
       }
-      n >>= 1;
+      reduce_rows<G, U, O / 2, N / 2>(part, g);
     } else {
-      part[0] += __shfl_xor(part[0], o, G);
+      part[0] += __shfl_xor(part[0], O, G);
+      reduce_rows<G, U, O / 2, 1>(part, g);
     }
   }
 }
@@ -402,26 +399,23 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     // ---- B: scoring of the queued ids. Each wave walks its rows in passes of RPW rows; the
     // loads of the next pass are issued before the current pass is folded (two register sets).
     // The block synchronises every PPC passes, when the candidate buffer may need compaction.
-    auto load_pass = [&](uint32_t rbase, uint32_t rows, int32_t (&rid)[U], uint4 (&w)[U][C]) {
+    auto load_pass = [&](uint32_t rbase, uint32_t rows, uint4 (&w)[U][C]) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t row = rbase + u * RPI + sub;
-        rid[u] = row < rows ? (int32_t)queue[row] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
+        const int32_t rid = row < rows ? (int32_t)queue[row] : -1;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const int ci = c * G + g;
-          if (rid[u] >= 0 && ci < p.nchunks)
-            w[u][c] = *reinterpret_cast<const uint4*>(p.Xs + (size_t)rid[u] * p.ld_bytes +
+          if (rid >= 0 && ci < p.nchunks)
+            w[u][c] = *reinterpret_cast<const uint4*>(p.Xs + (size_t)rid * p.ld_bytes +
                                                       (size_t)ci * 16);
           else
             w[u][c] = make_uint4(0u, 0u, 0u, 0u);
         }
       }
     };
-    auto fold_pass = [&](const int32_t (&rid)[U], const uint4 (&w)[U][C], uint64_t thr) {
+    auto fold_pass = [&](uint32_t rbase, uint32_t rows, const uint4 (&w)[U][C], uint64_t thr) {
       float part[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -430,11 +424,9 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         for (int c = 0; c < C; ++c) part[u] = fold_chunk<STORE>(part[u], qv[c], w[u][c]);
       }
       reduce_rows<G, U>(part, g);
-      const int row = reduced_row<G, U>(g);
-      int32_t myid = rid[0];
-#pragma unroll
-      for (int u = 1; u < U; ++u)
-        if (row == u) myid = rid[u];
+      // the lane that reports row `myrow` reads the row's id from the queue
+      const uint32_t myrow = rbase + (uint32_t)reduced_row<G, U>(g) * RPI + sub;
+      const int32_t myid = myrow < rows ? (int32_t)queue[myrow] : -1;
       float s = part[0];
       if constexpr (STORE == FPP_STORE_FP8) {
         if (myid >= 0) s = s * p.scale[myid];
@@ -455,17 +447,17 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       const uint32_t rows = st->qcount;
       for (uint32_t sb = 0; sb < rows || (last && sb == 0); sb += PPC * RPB) {
         const uint64_t thr = st->thr;
-        int32_t ra[U], rb[U];
         uint4 wa[U][C], wb[U][C];
-        load_pass(sb + wave * RPW, rows, ra, wa);
+        load_pass(sb + wave * RPW, rows, wa);
 #pragma unroll 1
         for (int ps = 0; ps < PPC; ps += 2) {
           // even pass folds set a while set b loads; odd pass the other way round
-          if (ps + 1 < PPC) load_pass(sb + (ps + 1) * RPB + wave * RPW, rows, rb, wb);
-          fold_pass(ra, wa, thr);
+          const uint32_t b0 = sb + ps * RPB + wave * RPW, b1 = b0 + RPB;
+          if (ps + 1 < PPC) load_pass(b1, rows, wb);
+          fold_pass(b0, rows, wa, thr);
           if (ps + 1 < PPC) {
-            if (ps + 2 < PPC) load_pass(sb + (ps + 2) * RPB + wave * RPW, rows, ra, wa);
-            fold_pass(rb, wb, thr);
+            if (ps + 2 < PPC) load_pass(b1 + RPB, rows, wa);
+            fold_pass(b1, rows, wb, thr);
           }
         }
         __syncthreads();
@@ -609,15 +601,11 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
 
     // ---- clear the dedup state
     if (st->overflow) {
-      // every entry's word: the bitmap returns to zero
-      for (int32_t pc = 0; pc < np; pc += kProbeChunk) {
-        const int npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
-        for (int i = wave; i < npc; i += kWaves) {
-          const uint32_t gb = pr[pc + i];
-          const uint32_t b0 = p.offsets[gb], b1 = p.offsets[gb + 1];
-          for (uint32_t e = b0 + lane; e < b1; e += 64) bitmap[p.ids[e] >> 5] = 0u;
-        }
-      }
+      // the whole bitmap returns to zero (coalesced 16-byte stores)
+      uint4* bm4 = reinterpret_cast<uint4*>(bitmap);
+      const int64_t n4 = p.bm_words / 4;
+      for (int64_t i = tid; i < n4; i += kBlock) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
+      for (int64_t i = n4 * 4 + tid; i < p.bm_words; i += kBlock) bitmap[i] = 0u;
       __threadfence();
     } else {
       // the set holds exactly the query's distinct ids (at most kSetLimit + kRound): reset slots
@@ -697,6 +685,10 @@ hipError_t dispatch_store(const ScoreParams& sp, int grid, hipStream_t s) {
 
 }  // namespace
 
+int64_t overflow_bitmap_words(const fpp_index* ix) {
+  return ((ix->n + 31) / 32 + 3) & ~(int64_t)3;   // per workgroup, a multiple of 16 bytes
+}
+
 int score_grid_blocks(const fpp_index* ix) {
   (void)ix;
   int dev = 0, cus = 0;
@@ -727,7 +719,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.scores_out = a.scores_out;
   sp.stats = a.stats;
   sp.gbitmap = a.gbitmap;
-  sp.bm_words = (ix->n + 31) / 32;
+  sp.bm_words = overflow_bitmap_words(ix);
   sp.short_ids = a.short_ids;
   sp.short_ld = a.short_ld;
   sp.lowp = a.store == FPP_STORE_FP32 ? 0 : 1;
