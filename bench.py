@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 QP_SWEEP = (10, 20, 50, 100, 200, 500, 1000, 2000, 5000, 10000, 20000)
+MIX_QPROBES = (20, 50, 200)
 
 
 def log(*a):
@@ -76,6 +77,42 @@ def traffic_per_call(dom):
     if rec.get("score_hip_sha256") != digest:
         return None
     return rec.get("hbm_bytes_per_call")
+
+
+def precision_report(torch, F, h, Xd, Qs, truth, k, qp):
+    """Per low-precision store: recall@10 with and without the FP32 rerank, the recall loss
+    against the plain FP32 path at the same qProbes, and the score error of the approximate
+    pass (no rerank) and of the reranked answer against float64 dot products (measurement only)."""
+    X64 = Xd.double()
+    Q64 = Qs.double()
+
+    def err(ids, sc):
+        idl = ids.long()
+        ok = idl >= 0
+        ex = (X64[idl.clamp_min(0)] * Q64[:, None, :]).sum(-1)
+        mag = (X64[idl.clamp_min(0)].abs() * Q64[:, None, :].abs()).sum(-1)
+        e = (sc.double() - ex).abs()[ok]
+        rel = e / ex.abs()[ok].clamp_min(1e-30)
+        return {"max_abs": float(e.max()), "mean_abs": float(e.mean()),
+                "max_rel": float(rel.max()), "median_rel": float(rel.median()),
+                "max_over_sum_abs": float((e / mag[ok].clamp_min(1e-30)).max())}
+
+    fi, fs = F.fpp_query(h, Qs, k, qp)
+    r32 = recall_at_10(fi.cpu().numpy(), truth)
+    out = {"qProbes": qp, "fp32": {"recall@10": round(r32, 4), "score_error": err(fi, fs)}}
+    for store in ("bf16", "fp8"):
+        ai, asc = F.fpp_query(h, Qs, k, qp, store=store, rerank_R=-1)
+        ri, rsc = F.fpp_query(h, Qs, k, qp, store=store)
+        ra = recall_at_10(ai.cpu().numpy(), truth)
+        rr = recall_at_10(ri.cpu().numpy(), truth)
+        out[store] = {"recall@10_no_rerank": round(ra, 4), "recall@10_rerank100": round(rr, 4),
+                      "recall_loss_vs_fp32_no_rerank": round(r32 - ra, 4),
+                      "recall_loss_vs_fp32_rerank100": round(r32 - rr, 4),
+                      "score_error_no_rerank": err(ai, asc), "score_error_rerank100": err(ri, rsc)}
+        log(f"precision {store}: recall no-rerank {ra:.4f} rerank {rr:.4f} (fp32 {r32:.4f}); "
+            f"approx max rel err {out[store]['score_error_no_rerank']['max_rel']:.2e}")
+    del X64, Q64
+    return out
 
 
 def timed_steps(torch, F, h, Qd, k, qp, store, steps, warmup):
@@ -225,7 +262,7 @@ def main():
 
     torch.cuda.synchronize()
     t = time.perf_counter()
-    h = F.fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l, stores=("bf16",))
+    h = F.fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l, stores=("bf16", "fp8"))
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t
     info = F.fpp_index_get_info(h)
@@ -248,8 +285,11 @@ def main():
                 break
         chosen.setdefault(store, args.qprobes or QP_SWEEP[-1])
 
+    precision = precision_report(torch, F, h, Xd, Qd[:ns].contiguous(), truth, k, chosen["bf16"])
+    chosen["fp8"] = chosen["bf16"]
+
     res = {}
-    for store in ("fp32", "bf16"):
+    for store in ("fp32", "bf16", "fp8"):
         qp = chosen[store]
         ms, stage = timed_steps(torch, F, h, Qd, k, qp, store, args.steps, args.warmup)
         _, _, st = F.fpp_query(h, Qd, k, qp, store=store, stats=True)
@@ -268,17 +308,20 @@ def main():
     if not args.no_serving:
         cap = res["bf16"]["qps"]
         qp = chosen["bf16"]
-        for frac in (0.25, 0.5, 0.8):
-            r = serving_run(torch, F, h, Qd, store="bf16", qps_offered=frac * cap,
-                            n_queries=args.serving_queries, k_choices=(k,), qp_choices=(qp,), seed=1)
-            serving[f"{frac}"] = r
-            log(f"serving {frac:.2f}x: offered {r['offered_qps']:.0f} achieved {r['achieved_qps']:.0f} "
+        # the workload's arrival rates (5k..200k queries/s), then fractions of the batch capacity
+        loads = [(f"{int(r)}", r) for r in (5e3, 5e4, 2e5)] + [(f"{f}", f * cap) for f in (0.25, 0.5, 0.8)]
+        for name, rate in loads:
+            nq = int(min(args.serving_queries, max(2_000, rate * 0.5)))
+            r = serving_run(torch, F, h, Qd, store="bf16", qps_offered=rate,
+                            n_queries=nq, k_choices=(k,), qp_choices=(qp,), seed=1)
+            serving[name] = r
+            log(f"serving {name}: offered {r['offered_qps']:.0f} achieved {r['achieved_qps']:.0f} "
                 f"p50 {r['p50_ms']:.2f} ms p99 {r['p99_ms']:.2f} ms batches {r['batches']}")
-        # mixed requests (k in {1, 10, 100}, 20/50/200 probes per table): offered at half the
-        # capacity a batch of that mix reaches
+        # mixed requests (k in {1, 10, 100}, qProbes in {20, 50, 200} in total): offered at half
+        # the capacity a batch of that mix reaches
         rng = np.random.default_rng(3)
         mk = rng.choice([1, 10, 100], size=w.Q.shape[0])
-        mq = rng.choice([20 * w.L, 50 * w.L, 200 * w.L], size=w.Q.shape[0])
+        mq = rng.choice(MIX_QPROBES, size=w.Q.shape[0])
         torch.cuda.synchronize()
         t = time.perf_counter()
         F.fpp_query_batch(h, Qd, mk, mq, store="bf16")
@@ -286,7 +329,7 @@ def main():
         mixed_cap = w.Q.shape[0] / (time.perf_counter() - t)
         mixed = serving_run(torch, F, h, Qd, store="bf16", qps_offered=0.5 * mixed_cap,
                             n_queries=min(args.serving_queries, 20_000),
-                            k_choices=(1, 10, 100), qp_choices=(20 * w.L, 50 * w.L, 200 * w.L), seed=2)
+                            k_choices=(1, 10, 100), qp_choices=MIX_QPROBES, seed=2)
         mixed["batch_capacity_qps"] = mixed_cap
         serving["mixed_k_qprobes"] = mixed
         log(f"serving mixed: achieved {mixed['achieved_qps']:.0f} p50 {mixed['p50_ms']:.2f} p99 {mixed['p99_ms']:.2f}")
@@ -327,7 +370,10 @@ def main():
                        "qProbes": chosen["fp32"], "recall@10": recalls.get(f"fp32@{chosen['fp32']}"),
                        "stage_ms": res["fp32"]["stage_ms"], "gather_gbs": round(res["fp32"]["gbs"], 1)},
         "bf16_batch": {"stage_ms": head["stage_ms"], "unique_per_query": head["unique"],
-                       "entries_per_query": head["entries"]},
+                       "entries_per_query": head["entries"], "gather_gbs": round(head["gbs"], 1)},
+        "fp8_batch": {"qps": round(res["fp8"]["qps"], 1), "ms_per_step": round(res["fp8"]["ms_per_step"], 4),
+                      "stage_ms": res["fp8"]["stage_ms"], "gather_gbs": round(res["fp8"]["gbs"], 1)},
+        "precision": precision,
         "serving": {"p50_ms": ser.get("p50_ms"), "p99_ms": ser.get("p99_ms"),
                     "achieved_qps": ser.get("achieved_qps"), "loads": serving},
         "build_s": round(build_s, 3),

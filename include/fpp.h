@@ -93,7 +93,8 @@ typedef struct fpp_query_opts {
   int32_t store;       /* store scored during the candidate pass: FPP_STORE_FP32 (exact scores, 0),
                           FPP_STORE_BF16 or FPP_STORE_FP8 (approximate; requires that store)     */
   int32_t rerank_R;    /* low-precision stores: short-list length re-scored exactly in FP32
-                          (0 = max(100, 2k)); 1 <= k <= R <= 512                                 */
+                          (0 = max(100, 2k)); k <= R <= 512. -1: no rerank, the top-k of the
+                          low-precision pass is returned with its approximate scores           */
   int64_t* stats;      /* optional device int64 [m][3]: probes, probed entries (with repeats),
                           unique candidates scored                                               */
   double* stage_ms;    /* optional host double [4]: milliseconds spent in hashing, probe

@@ -263,7 +263,7 @@ Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max
                           int32_t store, int32_t R_opt, int64_t budget, bool gbm_in_scratch) {
   Layout ly;
   ly.qcap = (int32_t)std::min<int64_t>(std::max(qp_max, 1), total_pairs(ix));
-  ly.short_ld = store == FPP_STORE_FP32 ? 0 : short_list_len(R_opt, k_max);
+  ly.short_ld = (store == FPP_STORE_FP32 || R_opt < 0) ? 0 : short_list_len(R_opt, k_max);
   const int64_t LF = (int64_t)ix->L * ix->l;
   const int64_t per_q = LF * ix->D * 6 + (int64_t)ly.qcap * 4 + 4 + (int64_t)ly.short_ld * 4 + 64;
   ly.mc = std::max<int64_t>(1, std::min<int64_t>(m, budget / per_q));
@@ -352,7 +352,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     a.scores_out = sc_c;
     FPP_HIP(launch_score(ix, a, s));
     FPP_TRY(mark());
-    if (qs.store != FPP_STORE_FP32) {
+    if (qs.store != FPP_STORE_FP32 && qs.R_opt >= 0) {
       FPP_HIP(launch_rerank(ix, Qc, d, mc, shortl, ly.short_ld, a.k_arr, qs.k_uniform, qs.R_opt,
                             off_c, ids_c, sc_c, s));
     }
@@ -367,7 +367,7 @@ static int query_common(const fpp_index* ix, QuerySpec& qs, hipStream_t s) {
   if (qs.m == 0) return FPP_OK;
   if (!qs.Q || !qs.ids_out || !qs.scores_out) return set_error("Q, ids_out and scores_out must be non-NULL"), FPP_EINVAL;
   FPP_TRY(check_store(ix, qs.store));
-  if (qs.R_opt < 0 || qs.R_opt > kMaxK) return set_error("rerank_R=%d out of [0, %d]", qs.R_opt, kMaxK), FPP_EINVAL;
+  if (qs.R_opt < -1 || qs.R_opt > kMaxK) return set_error("rerank_R=%d out of [-1, %d]", qs.R_opt, kMaxK), FPP_EINVAL;
 
   DeviceScratch host_arrays_unused;
   unsigned char* arrays = nullptr;

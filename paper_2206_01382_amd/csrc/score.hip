@@ -722,7 +722,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.bm_words = overflow_bitmap_words(ix);
   sp.short_ids = a.short_ids;
   sp.short_ld = a.short_ld;
-  sp.lowp = a.store == FPP_STORE_FP32 ? 0 : 1;
+  sp.lowp = (a.store == FPP_STORE_FP32 || a.rerank_R < 0) ? 0 : 1;
   sp.R_opt = a.rerank_R;
   const int grid = a.grid;
   switch (a.store) {

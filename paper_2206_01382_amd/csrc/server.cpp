@@ -347,7 +347,7 @@ int fpp_server_create(const fpp_index* ix, const fpp_server_opts* opts, fpp_serv
   if (o.n_streams < 1 || o.n_streams > 8) return set_error("n_streams=%d out of [1, 8]", o.n_streams), FPP_EINVAL;
   if (o.max_batch < 1) return set_error("max_batch=%d < 1", o.max_batch), FPP_EINVAL;
   if (o.scratch_bytes < 1) return set_error("scratch_bytes < 1"), FPP_EINVAL;
-  if (o.rerank_R < 0 || o.rerank_R > kMaxK) return set_error("rerank_R out of range"), FPP_EINVAL;
+  if (o.rerank_R < -1 || o.rerank_R > kMaxK) return set_error("rerank_R out of range"), FPP_EINVAL;
   FPP_TRY(check_store(ix, o.store));
   std::unique_ptr<fpp_server> sv(new fpp_server());
   sv->ix = ix;

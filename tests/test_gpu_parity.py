@@ -401,19 +401,46 @@ def test_query_low_precision_with_rerank(name, store):
     assert torch.equal(sc[same], fs[same])
 
 
-def test_fp8_decode_and_low_precision_score_error():
-    """Approximate scores of the low-precision stores against float64 on the dequantised store."""
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256"])
+@pytest.mark.parametrize("store", ["bf16", "fp8"])
+def test_query_low_precision_without_rerank(name, store):
+    """rerank_R = -1: the top-k of the approximate pass itself, scored on the dequantised store.
+
+    Scores are checked against float64 dot products with the dequantised rows (the FP32
+    accumulation bound), ids against exact search over the same candidates on that store."""
+    w, oi, h, Xd, Qd = built(name)
+    k, qp = 10, 8 * w["L"]
+    deq = O.dequantized_store(w["X"], store)
+    ids, sc = F().fpp_query(h, Qd, k, qp, store=store, rerank_R=-1)
+    gi, gs = ids.cpu().numpy(), sc.cpu().numpy()
+    m = w["Q"].shape[0]
+    oids = np.empty((m, k), dtype=np.int64)
+    osc = np.empty((m, k))
+    for r in range(m):
+        cand = O.candidates(oi, O.probes(oi, w["Q"][r], qp))
+        oids[r], osc[r] = O.topk_order(deq[cand] @ w["Q"][r].astype(np.float64), cand, k)
+    swaps = check_topk(deq, w["Q"], gi, gs, oids, osc, k, w["X"].shape[1])
+    assert swaps <= max(3, m * k // 50), swaps
+
+
+def test_rerank_of_exactly_k_is_a_reorder_with_exact_scores():
+    """With R = k the rerank reorders the approximate top-k; its scores are exact FP32 dot
+    products of the original rows (float64 within the FP32 accumulation bound)."""
     w, oi, h, Xd, Qd = built("l2_clustered")
+    d = w["X"].shape[1]
     for store in ("bf16", "fp8"):
-        deq = O.dequantized_store(w["X"], store)
+        ai, _ = F().fpp_query(h, Qd, 100, 8 * w["L"], store=store, rerank_R=-1)
         ids, sc = F().fpp_query(h, Qd, 100, 8 * w["L"], store=store, rerank_R=100)
-        # with R = k the rerank is a pure reorder of the short list: scores are exact FP32
-        gi = ids.cpu().numpy().astype(np.int64)
+        gi, ga, gs = ids.cpu().numpy().astype(np.int64), ai.cpu().numpy(), sc.cpu().numpy()
         for r in range(gi.shape[0]):
+            assert sorted(gi[r].tolist()) == sorted(ga[r].tolist())
             v = gi[r][gi[r] >= 0]
-            s64 = w["X"][v].astype(np.float64) @ w["Q"][r].astype(np.float64)
-            assert np.all(np.abs(sc.cpu().numpy()[r][: len(v)] - s64) <= 1e-6 * np.abs(s64) + 1e-6)
-        del deq
+            x64 = w["X"][v].astype(np.float64)
+            q64 = w["Q"][r].astype(np.float64)
+            s64 = x64 @ q64
+            tol = score_tol(s64, np.abs(x64 * q64).sum(1), d)
+            assert np.all(np.abs(gs[r][: len(v)] - s64) <= tol)
+            assert np.all(np.diff(gs[r][: len(v)]) <= 0)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -422,39 +449,41 @@ def test_full_size_c2_sampled():
     """n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3, in the launch
     configuration of the benchmark: sampled tables bit-exact, sampled queries' probes bit-exact,
     and their top-k equal to exact search over the candidates those probes select."""
-    w = synthdata.workload("c2_cluster_1m_d128", m=2000)
+    w = synthdata.workload("c2_cluster_1m_d128")
     Xd = torch.from_numpy(w.X).cuda()
     h = F().fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l)
     try:
         S = O.rotation_signs(42, w.L, w.l, 128)
         np.testing.assert_array_equal(F().fpp_debug_signs(h), S)
-        for t in (0, w.L - 1):
+        for t in (w.L - 1,):     # the last table: its ids sit after every other table's
+            print(f"full-size c2: oracle table {t}", flush=True)
             off, ids = F().fpp_debug_export_table(h, t)
             ooff, oids, _ = O.build_table(w.X, S[t], w.D, w.l, w.alpha, w.iProbes)
             np.testing.assert_array_equal(off, ooff)
             np.testing.assert_array_equal(ids, oids)
         Qd = torch.from_numpy(w.Q).cuda()
-        qp = 50 * w.L
-        gi, gs, st = F().fpp_query(h, Qd, 10, qp, stats=True)
-        gi, gs, st = gi.cpu().numpy(), gs.cpu().numpy(), st.cpu().numpy()
         tables = {}
         shell = O.Index(X=w.X, L=w.L, D=w.D, l=w.l, P=128, alpha=w.alpha, iProbes=w.iProbes, seed=42, signs=S)
         NB = O.n_buckets(w.D, w.l)
-        for r in (0, 1, 2, 1999):
-            pr = O.probes(shell, w.Q[r], qp)
-            gp = F().fpp_debug_probes(h, Qd[r:r + 1].contiguous(), qp).cpu().numpy()[0]
-            assert sorted(gp.tolist()) == sorted(pr.tolist())
-            cand = []
-            for p in pr:
-                t, b = divmod(int(p), NB)
-                if t not in tables:
-                    tables[t] = F().fpp_debug_export_table(h, t)
-                off, ids = tables[t]
-                cand.append(ids[off[b]:off[b + 1]])
-            cand = np.unique(np.concatenate(cand).astype(np.int64))
-            assert st[r, 2] == len(cand)
-            s64 = O.scores_f64(w.X, w.Q[r], cand)
-            ri, rs = O.topk_order(s64, cand, 10)
-            check_topk(w.X, w.Q[r:r + 1], gi[r:r + 1], gs[r:r + 1], ri[None], rs[None], 10, 128)
+        for qp in (50, 50 * w.L):     # the benchmark's total, and 50 per table
+            print(f"full-size c2: qProbes {qp}", flush=True)
+            gi, gs, st = F().fpp_query(h, Qd, 10, qp, stats=True)
+            gi, gs, st = gi.cpu().numpy(), gs.cpu().numpy(), st.cpu().numpy()
+            for r in (0, 1, 2, w.Q.shape[0] - 1):
+                pr = O.probes(shell, w.Q[r], qp)
+                gp = F().fpp_debug_probes(h, Qd[r:r + 1].contiguous(), qp).cpu().numpy()[0]
+                assert sorted(gp.tolist()) == sorted(pr.tolist())
+                cand = []
+                for p in pr:
+                    t, b = divmod(int(p), NB)
+                    if t not in tables:
+                        tables[t] = F().fpp_debug_export_table(h, t)
+                    off, ids = tables[t]
+                    cand.append(ids[off[b]:off[b + 1]])
+                cand = np.unique(np.concatenate(cand).astype(np.int64))
+                assert st[r, 2] == len(cand)
+                s64 = O.scores_f64(w.X, w.Q[r], cand)
+                ri, rs = O.topk_order(s64, cand, 10)
+                check_topk(w.X, w.Q[r:r + 1], gi[r:r + 1], gs[r:r + 1], ri[None], rs[None], 10, 128)
     finally:
         F().fpp_free_index(h)
