@@ -6,6 +6,7 @@
 // becomes a + b, the upper a - b) and reads the first D outputs y_i. Sign flips are XORs of the
 // sign bit; there are no multiplications, so the float32 results are those of that order.
 #include "fpp_internal.hpp"
+#include "lanes.hpp"
 
 namespace fpp {
 
@@ -28,15 +29,11 @@ __device__ __forceinline__ float flip(float v, uint32_t mask) {
 // Query side, everything in registers. An item (vector, function) spans LPI = P / E lanes of a
 // wavefront; lane x of the item holds the E consecutive elements j = x * E + e. Butterfly stages
 // h < E pair register e with e ^ h inside the lane; stages h >= E pair lane x with x ^ (h / E)
-// (the lower lane adds, the upper subtracts); stages run in the order h = 1, 2, ..., P/2.
+// (the lower lane adds, the upper subtracts) through DPP / row-swap lane exchanges; stages run in
+// the order h = 1, 2, ..., P/2.
 // The D keys (|y_i| bits << 32 | (0xffff - i) << 1 | sign) are then bitonic-sorted descending in
 // the same layout, which orders the list by (|y| desc, i asc) and carries the code bit.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m, int width) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m, width), hi = __shfl_xor((uint32_t)(v >> 32), m, width);
-  return ((uint64_t)hi << 32) | lo;
-}
-
 template <int P>
 struct QLayout {
   static constexpr int E = P < 8 ? P : (P / 64 > 8 ? P / 64 : 8);   // elements per lane
@@ -81,12 +78,10 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
     }
 #pragma unroll
     for (int hl = 1; hl < LPI; hl <<= 1) {
-      const bool upper = (li & hl) != 0;
+      // the upper lane of a pair computes w - v as w + (-v): the same rounded result
+      const uint32_t neg = (li & hl) ? 0x80000000u : 0u;
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const float w = __shfl_xor(v[e], hl, LPI);
-        v[e] = upper ? w - v[e] : v[e] + w;
-      }
+      for (int e = 0; e < E; ++e) v[e] = xor_lanes_n(v[e], hl) + flip(v[e], neg);
     }
   }
   uint64_t key[E];
@@ -120,7 +115,7 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
           const bool keep_max = ((li & (j / E)) == 0) == desc_lane;
 #pragma unroll
           for (int e = 0; e < E; ++e) {
-            const uint64_t o = shfl_xor_u64(key[e], j / E, LPI);
+            const uint64_t o = xor_lanes_n(key[e], j / E);
             key[e] = ((key[e] > o) == keep_max) ? key[e] : o;
           }
         }

@@ -53,13 +53,15 @@ struct Elems<FPP_STORE_FP8> {
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-// Exact value of an OCP E4M3 code (never NaN here).
-__device__ __forceinline__ float e4m3_val(uint32_t b) {
-  const uint32_t em = b & 0x7fu;
-  const float nrm = __uint_as_float((em << 20) + (120u << 23));
-  const float sub = (float)em * 0.001953125f;   // em * 2^-9, exact
-  const float mag = em >= 8u ? nrm : sub;
-  return __uint_as_float(__float_as_uint(mag) ^ ((b & 0x80u) << 24));
+// Exact values of the four OCP E4M3 codes of a word (bytes 0..3), by the gfx950 conversion
+// instruction, which decodes the OCP format (subnormals m * 2^-9 included) without rounding.
+__device__ __forceinline__ void e4m3x4(uint32_t w, float v[4]) {
+  const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, false);
+  const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w, true);
+  v[0] = lo[0];
+  v[1] = lo[1];
+  v[2] = hi[0];
+  v[3] = hi[1];
 }
 
 // Fold one 16-byte chunk of a stored row into the running partial p (fixed element order).
@@ -81,8 +83,10 @@ __device__ __forceinline__ float fold_chunk(float p, const float* qv, uint4 w) {
     const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      float v[4];
+      e4m3x4(ws[i], v);
 #pragma unroll
-      for (int b = 0; b < 4; ++b) p = __fmaf_rn(qv[4 * i + b], e4m3_val((ws[i] >> (8 * b)) & 0xffu), p);
+      for (int b = 0; b < 4; ++b) p = __fmaf_rn(qv[4 * i + b], v[b], p);
     }
   }
   return p;
@@ -348,8 +352,10 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
   constexpr int RPI = 64 / G;              // rows per wave instruction
   constexpr int RPW = U * RPI;             // rows per wave pass
   constexpr int RPB = RPW * kWaves;        // rows per block pass
-  constexpr int PPC = RPB >= 128 ? 1 : 128 / RPB;   // passes between block syncs (<= 128 rows)
-  static_assert(PPC * RPB <= kCandCap / 4, "candidate buffer too small");
+  constexpr int PPC = 2;                   // passes between block syncs (double-buffered)
+  // after a compaction at most max(kk, trig) <= kCandCap - PPC * RPB candidates remain, and one
+  // sync group appends at most PPC * RPB
+  static_assert(PPC * RPB <= kCandCap - kMaxK, "candidate buffer too small");
 
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* cand = reinterpret_cast<uint64_t*>(smem + kOffCand);
@@ -399,7 +405,13 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     // ---- B: scoring of the queued ids. Each wave walks its rows in passes of RPW rows; the
     // loads of the next pass are issued before the current pass is folded (two register sets).
     // The block synchronises every PPC passes, when the candidate buffer may need compaction.
-    auto load_pass = [&](uint32_t rbase, uint32_t rows, uint4 (&w)[U][C]) {
+    // loads the pass's row chunks and, for the FP8 store, the per-row scale of the row this lane
+    // reports after the reduction (issued with the rows, so its latency overlaps theirs)
+    auto load_pass = [&](uint32_t rbase, uint32_t rows, uint4 (&w)[U][C], float& scl) {
+      if constexpr (STORE == FPP_STORE_FP8) {
+        const uint32_t myrow = rbase + (uint32_t)reduced_row<G, U>(g) * RPI + sub;
+        scl = (myrow < rows && reports_row<G, U>(g)) ? p.scale[queue[myrow]] : 0.0f;
+      }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t row = rbase + u * RPI + sub;
@@ -415,7 +427,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         }
       }
     };
-    auto fold_pass = [&](uint32_t rbase, uint32_t rows, const uint4 (&w)[U][C], uint64_t thr) {
+    auto fold_pass = [&](uint32_t rbase, uint32_t rows, const uint4 (&w)[U][C], float scl, uint64_t thr) {
       float part[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -428,9 +440,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       const uint32_t myrow = rbase + (uint32_t)reduced_row<G, U>(g) * RPI + sub;
       const int32_t myid = myrow < rows ? (int32_t)queue[myrow] : -1;
       float s = part[0];
-      if constexpr (STORE == FPP_STORE_FP8) {
-        if (myid >= 0) s = s * p.scale[myid];
-      }
+      if constexpr (STORE == FPP_STORE_FP8) s = s * scl;
       const uint64_t key = make_key(s, myid);
       const bool pass = reports_row<G, U>(g) && myid >= 0 && key > thr;
       const uint64_t mask = __ballot(pass);
@@ -448,16 +458,17 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       for (uint32_t sb = 0; sb < rows || (last && sb == 0); sb += PPC * RPB) {
         const uint64_t thr = st->thr;
         uint4 wa[U][C], wb[U][C];
-        load_pass(sb + wave * RPW, rows, wa);
+        float sa = 0.0f, sbs = 0.0f;
+        load_pass(sb + wave * RPW, rows, wa, sa);
 #pragma unroll 1
         for (int ps = 0; ps < PPC; ps += 2) {
           // even pass folds set a while set b loads; odd pass the other way round
           const uint32_t b0 = sb + ps * RPB + wave * RPW, b1 = b0 + RPB;
-          if (ps + 1 < PPC) load_pass(b1, rows, wb);
-          fold_pass(b0, rows, wa, thr);
+          if (ps + 1 < PPC) load_pass(b1, rows, wb, sbs);
+          if (b0 < rows) fold_pass(b0, rows, wa, sa, thr);     // wave-uniform: no sync inside
           if (ps + 1 < PPC) {
-            if (ps + 2 < PPC) load_pass(b1 + RPB, rows, wa);
-            fold_pass(b1, rows, wb, thr);
+            if (ps + 2 < PPC) load_pass(b1 + RPB, rows, wa, sa);
+            if (b1 < rows) fold_pass(b1, rows, wb, sbs, thr);
           }
         }
         __syncthreads();
