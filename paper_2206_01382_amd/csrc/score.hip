@@ -18,6 +18,7 @@
 // The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
 // scores exactly in float32 from the FP32 store.
 #include "fpp_internal.hpp"
+#include "lanes.hpp"
 
 namespace fpp {
 namespace {
@@ -95,7 +96,7 @@ __device__ __forceinline__ float fold_chunk(float p, const float* qv, uint4 w) {
 template <int G>
 __device__ __forceinline__ float tree_sum(float p) {
 #pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) p += __shfl_xor(p, o, G);
+  for (int o = G / 2; o > 0; o >>= 1) p += xor_lanes_n(p, o);
   return p;
 }
 
@@ -151,11 +152,11 @@ __device__ __forceinline__ void reduce_rows(float (&part)[U], int g) {
       for (int i = 0; i < N / 2; ++i) {
         const float send = upper ? part[i] : part[i + N / 2];
         const float keep = upper ? part[i + N / 2] : part[i];
-        part[i] = keep + __shfl_xor(send, O, G);
+        part[i] = keep + xor_lanes<O>(send);
       }
       reduce_rows<G, U, O / 2, N / 2>(part, g);
     } else {
-      part[0] += __shfl_xor(part[0], O, G);
+      part[0] += xor_lanes<O>(part[0]);
       reduce_rows<G, U, O / 2, 1>(part, g);
     }
   }
