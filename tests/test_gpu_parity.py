@@ -79,21 +79,28 @@ def built(name):
     return _cache[name]
 
 
-def lane_layout(d):
-    nc = (d + 3) // 4
+EPC = {"fp32": 4, "bf16": 8, "fp8": 16}     # elements per 16-byte chunk of a stored row
+
+
+def lane_layout(d, store="fp32"):
+    """(G lanes per row, C chunks per lane) of the gather kernel for rows of d elements."""
+    nc = -(-d // EPC[store])
     for G in (8, 16, 32, 64):
         if nc <= G:
             return G, 1
     return 64, (2 if nc <= 128 else 4)
 
 
-def score_tol(s64, sabs, d):
-    G, C = lane_layout(d)
-    gam = (4 * C + math.log2(G) + 1) * 2.0 ** -24
-    return np.maximum(1e-6 * np.abs(s64), gam * sabs)
+def score_tol(s64, sabs, d, store="fp32"):
+    """FP32 error bound of one score: a chain of EPC*C fused multiply-adds per lane, log2(G)
+    tree levels, one rounding of slack (and the FP8 row-scale product), each at most 2^-24
+    relative to sum |q_j x_j|; never tighter than 1e-6 relative."""
+    G, C = lane_layout(d, store)
+    n = EPC[store] * C + math.log2(G) + 1 + (1 if store == "fp8" else 0)
+    return np.maximum(1e-6 * np.abs(s64), n * 2.0 ** -24 * sabs)
 
 
-def check_topk(X, Q, gi, gs, oi_ids, oi_sc, k, d):
+def check_topk(X, Q, gi, gs, oi_ids, oi_sc, k, d, store="fp32"):
     """ids equal up to adjudicated near-ties; scores within tolerance. Returns #swaps."""
     gi = gi.astype(np.int64)
     swaps = 0
@@ -106,7 +113,7 @@ def check_topk(X, Q, gi, gs, oi_ids, oi_sc, k, d):
         assert len(set(ids.tolist())) == len(ids)
         s64 = X64[ids] @ q
         sabs = np.abs(X64[ids] * q).sum(1)
-        tol = score_tol(s64, sabs, d)
+        tol = score_tol(s64, sabs, d, store)
         assert np.all(np.abs(gs[r][valid].astype(np.float64) - s64) <= tol), r
         assert np.all(np.isneginf(gs[r][~valid]))
         if not np.array_equal(gi[r], oi_ids[r]):
@@ -419,7 +426,7 @@ def test_query_low_precision_without_rerank(name, store):
     for r in range(m):
         cand = O.candidates(oi, O.probes(oi, w["Q"][r], qp))
         oids[r], osc[r] = O.topk_order(deq[cand] @ w["Q"][r].astype(np.float64), cand, k)
-    swaps = check_topk(deq, w["Q"], gi, gs, oids, osc, k, w["X"].shape[1])
+    swaps = check_topk(deq, w["Q"], gi, gs, oids, osc, k, w["X"].shape[1], store)
     assert swaps <= max(3, m * k // 50), swaps
 
 
