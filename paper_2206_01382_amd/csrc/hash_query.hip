@@ -41,30 +41,210 @@ struct QLayout {
   static constexpr int IPW = 64 / LPI;                              // items per wavefront
 };
 
-template <int P>
+// Exact 64-bit list key: |y| bits << 32 | (0xffff - i) << 1 | sign; descending order of keys is
+// (|y| desc, i asc), and the low bit carries the code (i or i + D).
+__device__ __forceinline__ uint64_t exact_key(float y, int i) {
+  const uint32_t neg = y >= 0.0f ? 0u : 1u;
+  return ((uint64_t)__float_as_uint(fabsf(y)) << 32) | ((uint32_t)(0xffff - i) << 1) | neg;
+}
+
+__device__ __forceinline__ void ce_desc(uint32_t& a, uint32_t& b) {
+  const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+  a = hi;
+  b = lo;
+}
+__device__ __forceinline__ void ce_desc(uint64_t& a, uint64_t& b) {
+  const bool sw = a < b;
+  const uint64_t x = sw ? b : a, y = sw ? a : b;
+  a = x;
+  b = y;
+}
+
+// Bitonic sort (descending) of the first D keys (D a power of two <= P) in the item layout: lane
+// li holds elements j0 + e, j0 = li * E. Stages k < E have compile-time directions; from k = E
+// on the direction is uniform over a lane, so lanes of ascending blocks complement their keys
+// (which reverses the order) and every compare-exchange keeps the larger value in front.
+template <int P, int E, int LPI>
+__device__ __forceinline__ void sort32_desc(uint32_t (&key)[E], int li, int j0, int D) {
+  uint32_t flipm = 0u;
+#pragma unroll
+  for (int k = 2; k <= P; k <<= 1) {
+    if (k <= D) {
+      if (k < E) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            if ((e & j) == 0) {
+              if ((e & k) == 0) ce_desc(key[e], key[e | j]);
+              else ce_desc(key[e | j], key[e]);
+            }
+          }
+        }
+      } else {
+        const uint32_t want = (j0 & k) == 0 ? 0u : 0xffffffffu;
+        const uint32_t x = want ^ flipm;
+#pragma unroll
+        for (int e = 0; e < E; ++e) key[e] ^= x;
+        flipm = want;
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          if (j < E) {
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+              if ((e & j) == 0) ce_desc(key[e], key[e | j]);
+          } else {
+            const bool lower = (li & (j / E)) == 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+              const uint32_t o = xor_lanes_n(key[e], j / E);
+              key[e] = lower ? (key[e] > o ? key[e] : o) : (key[e] > o ? o : key[e]);
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) key[e] ^= flipm;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bitonic sort (descending) of an item's first D exact keys in its LDS slot, with run-time
+// loops: the rare fallback when the transposition steps leave a list out of order.
+template <int E>
+__device__ __noinline__ void lds_sort64_desc(uint64_t* ks, int j0, int D) {
+  for (int k = 2; k <= D; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int i = j0 + e, p = i ^ j;
+        if (i < D && p > i) {
+          const uint64_t a = ks[i], b = ks[p];
+          if (((i & k) == 0) ? (a < b) : (a > b)) {
+            ks[i] = b;
+            ks[p] = a;
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+// Element p + 1 of the list from the next lane (wave_shl:1 DPP; lanes past the item or past D
+// are never used).
+__device__ __forceinline__ uint64_t from_next_lane(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x130, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x130, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t from_prev_lane(uint64_t v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x138, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x138, 0xF, 0xF, false);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+
+// One even and one odd transposition step (descending) over positions [0, D).
+template <int E, int LPI>
+__device__ __forceinline__ void repair_runs(uint64_t (&key)[E], int j0, int D) {
+#pragma unroll
+  for (int e = 0; e + 1 < E; e += 2)
+    if (j0 + e + 1 < D) ce_desc(key[e], key[e + 1]);
+#pragma unroll
+  for (int e = 1; e + 1 < E; e += 2)
+    if (j0 + e + 1 < D) ce_desc(key[e], key[e + 1]);
+  if constexpr (E % 2 == 0) {
+    // pair (last element of lane li, first element of lane li + 1): both lanes exchange the
+    // values before either changes; lane li keeps the larger, lane li + 1 the smaller
+    const uint64_t nxt = from_next_lane(key[0]);
+    const uint64_t prv = from_prev_lane(key[E - 1]);
+    const bool has_next = j0 + E < D;        // implies li + 1 < LPI (D <= P)
+    const bool has_prev = j0 > 0 && j0 < D;
+    if (has_next && key[E - 1] < nxt) key[E - 1] = nxt;
+    if (has_prev && prv < key[0]) key[0] = prv;
+  }
+}
+
+template <int E, int LPI>
+__device__ __forceinline__ bool out_of_order(const uint64_t (&key)[E], int j0, int D) {
+  bool bad = false;
+#pragma unroll
+  for (int e = 0; e + 1 < E; ++e)
+    if (j0 + e + 1 < D) bad |= key[e] <= key[e + 1];
+  const uint64_t nxt = from_next_lane(key[0]);
+  if (j0 + E < D) bad |= key[E - 1] <= nxt;
+  return bad;
+}
+
+template <int P, bool VEC>
 __global__ __launch_bounds__(256) void hash_query_kernel(
-    const float* __restrict__ V, int64_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
+    const float* __restrict__ V, uint32_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
     int LF, int D, float* __restrict__ la, uint16_t* __restrict__ lc) {
   constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI, IPW = QLayout<P>::IPW;
   const int lane = threadIdx.x & 63;
   const int li = lane % LPI;
-  const int64_t items = m * LF;
-  const int64_t item = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * IPW + lane / LPI;
-  if (((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * IPW >= items) return;   // whole wavefront
-  const bool valid = item < items;   // uniform over the item's lanes
-  const int64_t it = valid ? item : 0;
-  const int64_t q = it / LF;
-  const int tf = (int)(it - q * LF);
+  const uint32_t items = m * (uint32_t)LF;   // < 2^31 (checked by the launcher)
+  const uint32_t first = (blockIdx.x * 4u + (threadIdx.x >> 6)) * IPW;
+  if (first >= items) return;                // whole wavefront
+  const uint32_t item = first + lane / LPI;
+  const bool valid = item < items;           // uniform over the item's lanes
+  const uint32_t it = valid ? item : 0u;
+  const uint32_t q = it / (uint32_t)LF;
+  const int tf = (int)(it - q * (uint32_t)LF);
   const int j0 = li * E;
 
   float v[E];
+  const float* row = V + (size_t)q * ldv;
+  if constexpr (VEC && E % 4 == 0) {
+    // rows are 16-byte aligned: whole float4 groups below d, element loads in the tail group
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = (j0 + e < d) ? V[q * ldv + j0 + e] : 0.0f;
-  const uint32_t* sm = sign_mask + (size_t)tf * 3 * P + j0;
+    for (int g4 = 0; g4 < E / 4; ++g4) {
+      const int j = j0 + 4 * g4;
+      if (j + 4 <= d) {
+        const float4 x = *reinterpret_cast<const float4*>(row + j);
+        v[4 * g4] = x.x;
+        v[4 * g4 + 1] = x.y;
+        v[4 * g4 + 2] = x.z;
+        v[4 * g4 + 3] = x.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[4 * g4 + e] = (j + e < d) ? row[j + e] : 0.0f;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = (j0 + e < d) ? row[j0 + e] : 0.0f;
+  }
+  uint32_t smv[3][E];
+  {
+    const uint32_t* sm = sign_mask + (size_t)tf * 3 * P + j0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      if constexpr (E % 4 == 0) {
+#pragma unroll
+        for (int g4 = 0; g4 < E / 4; ++g4) {
+          const uint4 w = *reinterpret_cast<const uint4*>(sm + r * P + 4 * g4);
+          smv[r][4 * g4] = w.x;
+          smv[r][4 * g4 + 1] = w.y;
+          smv[r][4 * g4 + 2] = w.z;
+          smv[r][4 * g4 + 3] = w.w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) smv[r][e] = sm[r * P + e];
+      }
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = flip(v[e], sm[r * P + e]);
+    for (int e = 0; e < E; ++e) v[e] = flip(v[e], smv[r][e]);
 #pragma unroll
     for (int h = 1; h < E; h <<= 1) {
 #pragma unroll
@@ -84,55 +264,87 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
       for (int e = 0; e < E; ++e) v[e] = xor_lanes_n(v[e], hl) + flip(v[e], neg);
     }
   }
-  uint64_t key[E];
+  // ---- order the first D outputs by (|y| desc, i asc)
+  // 32-bit keys: |y| bits with the low log2(D) bits replaced by D - 1 - i, sorted descending; the
+  // order is exact except inside runs of equal truncated |y|, which hold their indices ascending.
+  // Exact values come back from LDS by index, one even and one odd transposition step on the
+  // exact 64-bit keys repair runs of two, and a wavefront whose lists are still out of order
+  // (a run of three or more) re-sorts the exact keys with the 64-bit network.
+  // LDS slot of the item: D floats (the signed outputs by index), reused as D 64-bit keys by the
+  // fallback sort
+  extern __shared__ uint64_t hq_lds[];
+  uint64_t* slot = hq_lds + (size_t)((threadIdx.x >> 6) * IPW + lane / LPI) * D;
+  float* yl = reinterpret_cast<float*>(slot);
+  const uint32_t imask = (uint32_t)D - 1u;
+  uint32_t k32[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int i = j0 + e;
-    const uint32_t neg = v[e] >= 0.0f ? 0u : 1u;
-    key[e] = i < D ? ((uint64_t)__float_as_uint(fabsf(v[e])) << 32) | ((uint32_t)(0xffff - i) << 1) | neg
-                   : 0ull;
-  }
-  // bitonic sort (descending) of the first D keys (D a power of two <= P)
-#pragma unroll
-  for (int k = 2; k <= P; k <<= 1) {
-    if (k <= D) {
-      // direction of element j0 + e in stage k: compile-time for k < E, lane-uniform for k >= E
-      const bool desc_lane = (j0 & k) == 0;
-#pragma unroll
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        if (j < E) {
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            if ((e & j) == 0) {
-              const bool desc = k < E ? ((e & k) == 0) : desc_lane;
-              const uint64_t a = key[e], b = key[e | j];
-              const bool sw = desc ? (a < b) : (b < a);
-              key[e] = sw ? b : a;
-              key[e | j] = sw ? a : b;
-            }
-          }
-        } else {
-          const bool keep_max = ((li & (j / E)) == 0) == desc_lane;
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            const uint64_t o = xor_lanes_n(key[e], j / E);
-            key[e] = ((key[e] > o) == keep_max) ? key[e] : o;
-          }
-        }
-      }
+    if (i < D) {
+      yl[i] = v[e];
+      k32[e] = (__float_as_uint(fabsf(v[e])) & ~imask) | (imask - (uint32_t)i);
+    } else {
+      k32[e] = 0u;
     }
+  }
+  sort32_desc<P, E, LPI>(k32, li, j0, D);
+  wave_lds_sync();
+  uint64_t key[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (j0 + e < D) {
+      const int i = (int)(imask - (k32[e] & imask));
+      key[e] = exact_key(yl[i], i);
+    } else {
+      key[e] = 0ull;
+    }
+  }
+  repair_runs<E, LPI>(key, j0, D);
+  if (__ballot(out_of_order<E, LPI>(key, j0, D)) != 0ull) {
+    // wave-uniform: every y has been read before the slots are overwritten
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < D) slot[j0 + e] = key[e];
+    wave_lds_sync();
+    lds_sort64_desc<E>(slot, j0, D);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < D) key[e] = slot[j0 + e];
   }
   if (!valid) return;
   float* ola = la + (size_t)item * D;
   uint16_t* olc = lc + (size_t)item * D;
+  uint32_t av[E], cv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t kk = key[e];
+    const int idx = 0xffff - (int)(((uint32_t)kk & 0x1ffffu) >> 1);
+    av[e] = (uint32_t)(kk >> 32);
+    cv[e] = (uint32_t)((kk & 1u) ? idx + D : idx);
+  }
+  if constexpr (E % 8 == 0) {
+    if (j0 + E <= D) {
+      // D >= E is a power of two: the lane's 4E + 2E bytes are 16-byte aligned
+#pragma unroll
+      for (int g4 = 0; g4 < E / 4; ++g4)
+        *reinterpret_cast<uint4*>(ola + j0 + 4 * g4) =
+            make_uint4(av[4 * g4], av[4 * g4 + 1], av[4 * g4 + 2], av[4 * g4 + 3]);
+#pragma unroll
+      for (int g8 = 0; g8 < E / 8; ++g8) {
+        const uint32_t* c = cv + 8 * g8;
+        *reinterpret_cast<uint4*>(olc + j0 + 8 * g8) =
+            make_uint4(c[0] | (c[1] << 16), c[2] | (c[3] << 16), c[4] | (c[5] << 16), c[6] | (c[7] << 16));
+      }
+      return;
+    }
+  }
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = j0 + e;
     if (p < D) {
-      const uint64_t kk = key[e];
-      const int idx = 0xffff - (int)(((uint32_t)kk & 0x1ffffu) >> 1);
-      ola[p] = __uint_as_float((uint32_t)(kk >> 32));
-      olc[p] = (uint16_t)((kk & 1u) ? idx + D : idx);
+      ola[p] = __uint_as_float(av[e]);
+      olc[p] = (uint16_t)cv[e];
     }
   }
 }
@@ -157,11 +369,19 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
   if (m <= 0) return hipSuccess;
   const int LF = ix->L * ix->l;
   const int64_t items = m * LF;
+  if (items >= (int64_t)1 << 31) return hipErrorInvalidValue;   // callers chunk the queries
+  const bool vec = (ix->d % 4 == 0) && (ldv % 4 == 0) && ((uintptr_t)V % 16 == 0);
 #define FPP_HQ(PP)                                                                             \
   case PP: {                                                                                   \
     const int64_t waves = (items + QLayout<PP>::IPW - 1) / QLayout<PP>::IPW;                   \
-    hipLaunchKernelGGL(hash_query_kernel<PP>, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, \
-                       V, m, ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc);                    \
+    const dim3 grid((unsigned)((waves + 3) / 4));                                              \
+    const size_t lds = (size_t)4 * QLayout<PP>::IPW * ix->D * sizeof(uint64_t);               \
+    if (vec)                                                                                   \
+      hipLaunchKernelGGL((hash_query_kernel<PP, true>), grid, dim3(256), lds, s, V,            \
+                         (uint32_t)m, ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc);           \
+    else                                                                                       \
+      hipLaunchKernelGGL((hash_query_kernel<PP, false>), grid, dim3(256), lds, s, V,           \
+                         (uint32_t)m, ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc);           \
     break;                                                                                     \
   }
   switch (ix->P) {

@@ -143,6 +143,65 @@ def test_query_hash_lists_bit_exact(name):
             np.testing.assert_array_equal(c[:, t, f], hl.code)
 
 
+def _near_tie_vectors(d, rng):
+    """Vectors whose projections tie exactly or nearly (equal in the leading bits): basis
+    vectors, constant vectors, a*e0 + b*e1 with tiny b, repeated coordinates, zero."""
+    out = [np.zeros(d), np.ones(d) / math.sqrt(d)]
+    for i in (0, 1, d - 1):
+        e = np.zeros(d)
+        e[i] = 1.0
+        out.append(e)
+    for b in (1e-9, 1e-7, 3e-7, 1e-6, 4e-6, 1e-5, 1e-4, 1e-3):
+        x = np.zeros(d)
+        x[0], x[1] = 1.0, b
+        out.append(x)
+        y = np.zeros(d)
+        y[0], y[1], y[min(2, d - 1)] = 1.0, b, -2.5 * b
+        out.append(y)
+    for _ in range(6):
+        x = rng.standard_normal(d)
+        x[rng.integers(0, d, size=d // 2)] = x[0]          # many equal coordinates
+        out.append(x)
+        z = rng.standard_normal(d)
+        z = z + 1e-6 * rng.standard_normal(d)              # generic
+        out.append(z)
+    return np.stack(out).astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64", "pad_d100_D16"])
+def test_query_hash_lists_near_ties_bit_exact(name):
+    """Lists whose |y| values tie exactly or agree in their leading bits (the order then rests
+    on the full float bits and the index) are bit-exact."""
+    w, oi, h, Xd, Qd = built(name)
+    V = _near_tie_vectors(w["X"].shape[1], np.random.default_rng(5))
+    a, c = F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda())
+    a, c = a.cpu().numpy(), c.cpu().numpy()
+    for t in range(w["L"]):
+        for f in range(w["l"]):
+            hl = O.hash_lists(V, oi.signs[t, f], w["D"])
+            np.testing.assert_array_equal(a[:, t, f].view(np.uint32), hl.a.view(np.uint32))
+            np.testing.assert_array_equal(c[:, t, f], hl.code)
+
+
+def test_query_hash_lists_d128_D128_bit_exact():
+    """The headline shape (d = P = D = 128, l = 2) on random and near-tie vectors."""
+    X, Q = synthdata.clustered_sphere(2_000, 128, 200, 20, 0.3, seed=21)
+    Xd = torch.from_numpy(X).cuda()
+    h = F().fpp_build_index(Xd, 4, 128, 0.3, 3, 99, l=2)
+    try:
+        V = np.concatenate([Q, _near_tie_vectors(128, np.random.default_rng(6))])
+        a, c = F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda())
+        a, c = a.cpu().numpy(), c.cpu().numpy()
+        S = O.rotation_signs(99, 4, 2, 128)
+        for t in range(4):
+            for f in range(2):
+                hl = O.hash_lists(V, S[t, f], 128)
+                np.testing.assert_array_equal(a[:, t, f].view(np.uint32), hl.a.view(np.uint32))
+                np.testing.assert_array_equal(c[:, t, f], hl.code)
+    finally:
+        F().fpp_free_index(h)
+
+
 @pytest.mark.parametrize("name", list(CONFIGS))
 def test_build_records_bit_exact(name):
     w, oi, h, Xd, Qd = built(name)
