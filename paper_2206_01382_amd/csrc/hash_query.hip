@@ -94,11 +94,14 @@ __device__ __forceinline__ void sort32_desc(uint32_t (&key)[E], int li, int j0, 
             for (int e = 0; e < E; ++e)
               if ((e & j) == 0) ce_desc(key[e], key[e | j]);
           } else {
-            const bool lower = (li & (j / E)) == 0;
+            // median of (key, partner, 0 or ~0): the larger in the lower lane, the smaller above
+            const uint32_t lim = (li & (j / E)) == 0 ? 0xffffffffu : 0u;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
               const uint32_t o = xor_lanes_n(key[e], j / E);
-              key[e] = lower ? (key[e] > o ? key[e] : o) : (key[e] > o ? o : key[e]);
+              const uint32_t mx = key[e] > o ? key[e] : o, mn = key[e] > o ? o : key[e];
+              const uint32_t c = mx < lim ? mx : lim;
+              key[e] = mn > c ? mn : c;
             }
           }
         }
@@ -241,10 +244,17 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
       }
     }
   }
+  // Cross-lane stages use one fused multiply-add: v + w * (+1) in the lower lane of a pair and
+  // v - w (= -(w - v), the same rounding) in the upper one, so an upper lane holds the negated
+  // value. Partners of a later stage differ only in that stage's lane bit, so they carry the
+  // same sign; after a round lane li holds (-1)^popcount(li) times the true values, which the
+  // next round's sign flip and the end of the rotation undo with one XOR of the sign bit. (Only
+  // the sign of a zero can differ, and neither |y| nor the code rule y >= 0 sees it.)
+  const uint32_t lane_sign = (__popc((unsigned)li) & 1) ? 0x80000000u : 0u;
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = flip(v[e], smv[r][e]);
+    for (int e = 0; e < E; ++e) v[e] = flip(v[e], r == 0 ? smv[r][e] : (smv[r][e] ^ lane_sign));
 #pragma unroll
     for (int h = 1; h < E; h <<= 1) {
 #pragma unroll
@@ -258,12 +268,13 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
     }
 #pragma unroll
     for (int hl = 1; hl < LPI; hl <<= 1) {
-      // the upper lane of a pair computes w - v as w + (-v): the same rounded result
-      const uint32_t neg = (li & hl) ? 0x80000000u : 0u;
+      const float mul = (li & hl) ? -1.0f : 1.0f;
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = xor_lanes_n(v[e], hl) + flip(v[e], neg);
+      for (int e = 0; e < E; ++e) v[e] = __builtin_fmaf(xor_lanes_n(v[e], hl), mul, v[e]);
     }
   }
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = flip(v[e], lane_sign);
   // ---- order the first D outputs by (|y| desc, i asc)
   // 32-bit keys: |y| bits with the low log2(D) bits replaced by D - 1 - i, sorted descending; the
   // order is exact except inside runs of equal truncated |y|, which hold their indices ascending.

@@ -14,15 +14,15 @@ __device__ __forceinline__ uint32_t xor_lanes(uint32_t v) {
   static_assert(X == 1 || X == 2 || X == 4 || X == 8 || X == 16 || X == 32, "butterfly distance");
   const int s = (int)v;
   if constexpr (X == 1) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, s, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0xB1, 0xF, 0xF, true);   // quad_perm 1,0,3,2
   } else if constexpr (X == 2) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, s, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x4E, 0xF, 0xF, true);   // quad_perm 2,3,0,1
   } else if constexpr (X == 4) {
     // mirror within 8 lanes (x -> 7 - x), then reverse each quad (x -> x ^ 3): x -> x ^ 4
-    const int m = __builtin_amdgcn_update_dpp(0, s, 0x141, 0xF, 0xF, false);      // row_half_mirror
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, m, 0x1B, 0xF, 0xF, false);   // quad_perm 3,2,1,0
+    const int m = __builtin_amdgcn_mov_dpp(s, 0x141, 0xF, 0xF, true);      // row_half_mirror
+    return (uint32_t)__builtin_amdgcn_mov_dpp(m, 0x1B, 0xF, 0xF, true);   // quad_perm 3,2,1,0
   } else if constexpr (X == 8) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, s, 0x128, 0xF, 0xF, false);  // row_ror:8
+    return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x128, 0xF, 0xF, true);  // row_ror:8
   } else if constexpr (X == 16) {
     // after the swap, even rows of r[1] hold the odd rows' values and odd rows of r[0] the
     // even rows' values
