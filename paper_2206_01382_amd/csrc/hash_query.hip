@@ -36,7 +36,7 @@ __device__ __forceinline__ float flip(float v, uint32_t mask) {
 // ------------------------------------------------------------------------------------------
 template <int P>
 struct QLayout {
-  static constexpr int E = P < 8 ? P : (P / 64 > 8 ? P / 64 : 8);   // elements per lane
+  static constexpr int E = P < 16 ? P : (P / 64 > 16 ? P / 64 : 16);  // elements per lane
   static constexpr int LPI = P / E;                                 // lanes per item
   static constexpr int IPW = 64 / LPI;                              // items per wavefront
 };
@@ -185,10 +185,13 @@ __device__ __forceinline__ bool out_of_order(const uint64_t (&key)[E], int j0, i
   return bad;
 }
 
-template <int P, bool VEC>
+// VEC: rows of V are 16-byte aligned and d % 4 == 0. FULL: D == P (every output is listed), which
+// turns the per-element bounds tests into constants.
+template <int P, bool VEC, bool FULL>
 __global__ __launch_bounds__(256) void hash_query_kernel(
     const float* __restrict__ V, uint32_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
-    int LF, int D, float* __restrict__ la, uint16_t* __restrict__ lc) {
+    int LF, int D_arg, float* __restrict__ la, uint16_t* __restrict__ lc) {
+  const int D = FULL ? P : D_arg;
   constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI, IPW = QLayout<P>::IPW;
   const int lane = threadIdx.x & 63;
   const int li = lane % LPI;
@@ -382,17 +385,18 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
   const int64_t items = m * LF;
   if (items >= (int64_t)1 << 31) return hipErrorInvalidValue;   // callers chunk the queries
   const bool vec = (ix->d % 4 == 0) && (ldv % 4 == 0) && ((uintptr_t)V % 16 == 0);
+  const bool full = ix->D == ix->P;
+#define FPP_HQ_LAUNCH(PP, VV, FF)                                                              \
+  hipLaunchKernelGGL((hash_query_kernel<PP, VV, FF>), grid, dim3(256), lds, s, V, (uint32_t)m,   \
+                     ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc)
 #define FPP_HQ(PP)                                                                             \
   case PP: {                                                                                   \
     const int64_t waves = (items + QLayout<PP>::IPW - 1) / QLayout<PP>::IPW;                   \
     const dim3 grid((unsigned)((waves + 3) / 4));                                              \
     const size_t lds = (size_t)4 * QLayout<PP>::IPW * ix->D * sizeof(uint64_t);               \
-    if (vec)                                                                                   \
-      hipLaunchKernelGGL((hash_query_kernel<PP, true>), grid, dim3(256), lds, s, V,            \
-                         (uint32_t)m, ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc);           \
-    else                                                                                       \
-      hipLaunchKernelGGL((hash_query_kernel<PP, false>), grid, dim3(256), lds, s, V,           \
-                         (uint32_t)m, ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc);           \
+    if (vec && full) FPP_HQ_LAUNCH(PP, true, true);                                            \
+    else if (vec) FPP_HQ_LAUNCH(PP, true, false);                                              \
+    else FPP_HQ_LAUNCH(PP, false, false);                                                      \
     break;                                                                                     \
   }
   switch (ix->P) {
@@ -401,6 +405,7 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
     default: return hipErrorInvalidValue;
   }
 #undef FPP_HQ
+#undef FPP_HQ_LAUNCH
   return hipGetLastError();
 }
 
