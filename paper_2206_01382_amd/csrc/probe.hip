@@ -13,21 +13,27 @@
 //     (table, i, j) order until qProbes are selected.
 // One workgroup per query; thread x walks tables x, x + 128, ... with the first M entries of
 // every sorted list staged in LDS (entries past M are read from device memory).
+#include <algorithm>
+
 #include "fpp_internal.hpp"
 
 namespace fpp {
 namespace {
 
 constexpr int kProbeThreads = 128;
+constexpr int kRankTables = 1024;   // rank the tables' best pairs for the lower bound up to this L
 constexpr int kProbeWaves = kProbeThreads / 64;
 
-// Sorted-list access: the first M entries of every list of the query sit in LDS.
+// Sorted-list access: the first M entries of every list of the query sit in LDS. List f of table
+// t (list index l * t + f) is LDS row f * L + t with a row stride of M + 1 words (M is a power of
+// two), so the threads of a wavefront, which walk consecutive tables, hit distinct banks.
 struct Lists {
-  const float* lds;     // [LF][M]
+  const float* lds;     // [l][L][M + 1]
   const float* glob;    // [LF][D] of this query
-  int M, D;
+  int M, D, L, l;
   __device__ __forceinline__ float get(int list, int i) const {
-    return i < M ? lds[list * M + i] : glob[(size_t)list * D + i];
+    const int t = l == 2 ? list >> 1 : list, f = l == 2 ? list & 1 : 0;
+    return i < M ? lds[(f * L + t) * (M + 1) + i] : glob[(size_t)list * D + i];
   }
 };
 
@@ -111,19 +117,51 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* red = reinterpret_cast<uint64_t*>(smem);        // kProbeWaves words
-  float* pre = reinterpret_cast<float*>(smem + 64);         // [LF][M]
+  float* pre = reinterpret_cast<float*>(smem + 64);         // [l][L][M + 1] list prefixes
   const int64_t q = blockIdx.x;
   if (q >= m) return;   // uniform
   const int tid = threadIdx.x;
   const int LF = L * l;
   const float* Aq = la + (size_t)q * LF * D;
   const uint16_t* Cq = lc + (size_t)q * LF * D;
-  for (int i = tid; i < LF * M; i += kProbeThreads) {
-    const int list = i / M, e = i - list * M;
-    pre[i] = Aq[(size_t)list * D + e];
+  float* tops = pre + (size_t)l * L * (M + 1);             // [L] best pair of every table
+  float* sel = tops + L;                                    // one value
+  if (M % 4 == 0) {
+    // 16-byte loads, four per thread in flight before their LDS stores
+    const int per = M / 4, total4 = LF * per;
+    for (int b = tid; b < total4; b += 4 * kProbeThreads) {
+      float4 r[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = b + u * kProbeThreads;
+        if (i < total4) {
+          const int list = i / per, e4 = i - list * per;
+          r[u] = *reinterpret_cast<const float4*>(Aq + (size_t)list * D + 4 * e4);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = b + u * kProbeThreads;
+        if (i < total4) {
+          const int list = i / per, e4 = i - list * per;
+          const int t = l == 2 ? list >> 1 : list, f = l == 2 ? list & 1 : 0;
+          float* row = pre + (f * L + t) * (M + 1) + 4 * e4;
+          row[0] = r[u].x;
+          row[1] = r[u].y;
+          row[2] = r[u].z;
+          row[3] = r[u].w;
+        }
+      }
+    }
+  } else {
+    for (int i = tid; i < LF * M; i += kProbeThreads) {
+      const int list = i / M, e = i - list * M;
+      const int t = l == 2 ? list >> 1 : list, f = l == 2 ? list & 1 : 0;
+      pre[(f * L + t) * (M + 1) + e] = Aq[(size_t)list * D + e];
+    }
   }
   __syncthreads();
-  const Lists ls{pre, Aq, M, D};
+  const Lists ls{pre, Aq, M, D, L, l};
 
   const uint64_t total = (uint64_t)L * (l == 1 ? (uint64_t)D : (uint64_t)D * D);
   const int64_t want = qp_arr ? qp_arr[q] : qp_uniform;
@@ -154,9 +192,25 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     }
     mx = fmaxf(mx, top);
     mn = fminf(mn, bound);
+    tops[t] = top;
   }
-  mx = block_max(mx, reinterpret_cast<float*>(red));
+  mx = block_max(mx, reinterpret_cast<float*>(red));      // (its barriers publish `tops`)
   mn = -block_max(-mn, reinterpret_cast<float*>(red));
+  if (qP <= (uint64_t)L && L <= kRankTables) {
+    // A tighter lo: the table of rank qP - 1 in (best pair desc, table asc) order. The qP tables
+    // ranked before or at it each hold a pair scoring >= its best pair, so cnt(lo) >= qP.
+    for (int t = tid; t < L; t += kProbeThreads) {
+      const float v = tops[t];
+      int r = 0;
+      for (int u = 0; u < L; ++u) {
+        const float w = tops[u];
+        r += (w > v || (w == v && u < t)) ? 1 : 0;
+      }
+      if ((uint64_t)r == qP - 1) *sel = v;
+    }
+    __syncthreads();
+    mn = fmaxf(mn, *sel);
+  }
 
   // Counts are capped at qP + 1 per table: a capped sum is >= qP exactly when the true sum is,
   // and equals qP only when no table was capped, so every decision below is the uncapped one.
@@ -239,14 +293,16 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
 }  // namespace
 
 // Prefix length of each sorted list staged in LDS: enough for about twice the average number of
-// probes per table, at most D and at most 60 KB of LDS per query.
+// probes per table, at most D and at most 60 KB of LDS per query. Small prefixes keep many
+// queries resident per CU, which hides the latency of the walks; entries past the prefix come
+// from device memory.
 int probe_prefix(const fpp_index* ix, int32_t qcap) {
-  const int LF = ix->L * ix->l;
+  const int64_t LF = (int64_t)ix->L * ix->l;
   int want = 16;
   const int64_t per_t = (2LL * qcap + ix->L - 1) / ix->L;
   while (want < per_t && want < ix->D) want <<= 1;
   if (want > ix->D) want = ix->D;
-  while (want > 1 && (int64_t)LF * want * 4 > 60 * 1024) want >>= 1;
+  while (want > 1 && (LF * (want + 1) + ix->L + 1) * 4 > 60 * 1024) want >>= 1;
   return want;
 }
 
@@ -255,7 +311,12 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
                                uint32_t* probes, int32_t* nprobe, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const int M = probe_prefix(ix, qcap);
-  const size_t lds = 64 + (size_t)ix->L * ix->l * M * 4;
+  const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + ix->L + 1) * 4;
+  if (lds > 64 * 1024) {   // at most 82 KB (L = 4096, l = 2, M = 1), within the 160 KB of a CU
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(probe_kernel),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(probe_kernel, dim3((unsigned)m), dim3(kProbeThreads), lds, s, la, lc, m, ix->L,
                      ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probes, nprobe);
   return hipGetLastError();
