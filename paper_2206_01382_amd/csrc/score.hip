@@ -212,7 +212,7 @@ __device__ __forceinline__ void chunk_stages(uint64_t& a, uint64_t& b, int i0, i
 
 // Block-wide bitonic sort (descending) of n keys in LDS, n a power of two >= 128. Stages with a
 // partner distance below 128 run in registers (two keys per lane, shuffles), the others in LDS.
-__device__ void block_sort_desc(uint64_t* key, int n) {
+__device__ __noinline__ void block_sort_desc(uint64_t* key, int n) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int chunks = n >> 7;
   for (int c = wave; c < chunks; c += kWaves) {
