@@ -47,10 +47,12 @@ def recall_at_10(found: np.ndarray, truth: np.ndarray) -> float:
 def ground_truth(torch, Xd, Qs, k):
     """Exact top-k by float64 inner products on the device (measurement only)."""
     X64 = Xd.double()
+    step = max(1, min(250, int(2e9 // (8 * Xd.shape[0]))))   # at most ~2 GB of scores at once
     out = []
-    for s in range(0, Qs.shape[0], 250):
-        S = Qs[s:s + 250].double() @ X64.T
+    for s in range(0, Qs.shape[0], step):
+        S = Qs[s:s + step].double() @ X64.T
         out.append(torch.topk(S, k, dim=1).indices.cpu().numpy())
+        del S
     del X64
     return np.concatenate(out)
 
@@ -80,7 +82,7 @@ def traffic_per_call(dom):
     return rec.get("hbm_bytes_per_call")
 
 
-def precision_report(torch, F, h, Xd, Qs, truth, k, qp):
+def precision_report(torch, F, h, Xd, Qs, truth, k, qp, stores=("bf16", "fp8")):
     """Per low-precision store: recall@10 with and without the FP32 rerank, the recall loss
     against the plain FP32 path at the same qProbes, and the score error of the approximate
     pass (no rerank) and of the reranked answer against float64 dot products (measurement only)."""
@@ -101,7 +103,7 @@ def precision_report(torch, F, h, Xd, Qs, truth, k, qp):
     fi, fs = F.fpp_query(h, Qs, k, qp)
     r32 = recall_at_10(fi.cpu().numpy(), truth)
     out = {"qProbes": qp, "fp32": {"recall@10": round(r32, 4), "score_error": err(fi, fs)}}
-    for store in ("bf16", "fp8"):
+    for store in stores:
         ai, asc = F.fpp_query(h, Qs, k, qp, store=store, rerank_R=-1)
         ri, rsc = F.fpp_query(h, Qs, k, qp, store=store)
         ra = recall_at_10(ai.cpu().numpy(), truth)
@@ -228,6 +230,72 @@ def cpu_baseline(w, qpt, k):
     }
 
 
+def run_secondary(args, name):
+    """One JSON line for the precision-form (n = 1M, d = 300) or the large (n = 10M, d = 96)
+    workload: build time, recall of each store with and without rerank, score errors and the
+    query rate of each store at the smallest swept qProbes reaching recall@10 >= 0.9."""
+    import torch
+
+    import paper_2206_01382_amd as F
+    import synthdata
+
+    F.lib()
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    w = synthdata.workload(name)
+    log(f"data {w.X.shape} queries {w.Q.shape} in {time.perf_counter() - t:.1f}s")
+    Xd = torch.from_numpy(w.X).cuda()
+    Qd = torch.from_numpy(w.Q).cuda()
+    k = w.k
+    stores = ("bf16", "fp8") if name.startswith("c3") else ("fp8",)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    h = F.fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l, stores=stores)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t
+    info = F.fpp_index_get_info(h)
+    log(f"build {build_s:.3f}s ids {info['total_ids']} max bucket {info['max_bucket']} "
+        f"device {info['device_bytes'] / 2**30:.2f} GiB")
+    ns = min(Qd.shape[0], 1000 if w.X.shape[0] > 5_000_000 else Qd.shape[0])
+    Qs = Qd[:ns].contiguous()
+    truth = ground_truth(torch, Xd, Qs, k)
+    sweep = sorted({v * w.L for v in w.qprobes_per_table} | set(w.qprobes_per_table))
+    if args.qprobes:
+        sweep = [args.qprobes]
+    recalls, chosen = {}, None
+    for qp in sweep:
+        row = {}
+        for store in ("fp32",) + stores:
+            ids, _ = F.fpp_query(h, Qs, k, qp, store=store)
+            row[store] = round(recall_at_10(ids.cpu().numpy(), truth), 4)
+        recalls[str(qp)] = row
+        log(f"recall qProbes={qp}: {row}")
+        if row[stores[-1]] >= 0.9:
+            chosen = qp
+            break
+    if chosen is None:
+        chosen = sweep[-1]
+    precision = precision_report(torch, F, h, Xd, Qs, truth, k, chosen, stores=stores)
+    res = {}
+    for store in ("fp32",) + stores:
+        ms, med, stage = timed_steps(torch, F, h, Qd, k, chosen, store, args.steps, args.warmup)
+        _, _, st = F.fpp_query(h, Qd, k, chosen, store=store, stats=True)
+        st = st.cpu().numpy()
+        byt = algorithmic_bytes(st, w.X.shape[1], store, k, max(100, 2 * k))
+        res[store] = {"qps": round(Qd.shape[0] / (ms / 1e3), 1), "ms_per_call": round(ms, 3),
+                      "median_ms": round(med, 3), "stage_ms": [round(x, 4) for x in stage],
+                      "gather_gbs": round(byt / (stage[2] / 1e3) / 1e9, 1),
+                      "unique_per_query": float(st[:, 2].mean())}
+        log(f"{store}: {ms:.3f} ms per {Qd.shape[0]} queries; stages {stage.round(3)} gather {res[store]['gather_gbs']} GB/s")
+    F.fpp_free_index(h)
+    out = {"workload": name, "n": int(w.X.shape[0]), "d": int(w.X.shape[1]), "queries": int(Qd.shape[0]),
+           "L": w.L, "D": w.D, "l": w.l, "alpha": w.alpha, "iProbes": w.iProbes, "k": k,
+           "build_s": round(build_s, 3), "index_ids": info["total_ids"], "max_bucket": info["max_bucket"],
+           "device_gib": round(info["device_bytes"] / 2**30, 3), "recall_sample": ns,
+           "qProbes": chosen, "recall_sweep": recalls, "precision": precision, "stores": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,10 +308,16 @@ def main():
                     help="duration per offered load (at most 100,000 queries per load)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 1 GiB device-to-device copy (scale for rocprofv3 byte counters)")
+    ap.add_argument("--workload", default="c2", choices=("c2", "c3", "c5"),
+                    help="c2: the headline (n=1M, d=128); c3: precision form (n=1M, d=300); "
+                         "c5: n=10M, d=96 with FP8 (each prints its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus N>1 is not supported"}), flush=True)
         sys.exit(2)
+    if args.workload != "c2":
+        run_secondary(args, {"c3": "c3_cluster_1m_d300", "c5": "c5_cluster_10m_d96"}[args.workload])
+        return
 
     import torch
 
