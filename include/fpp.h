@@ -57,7 +57,23 @@ typedef struct fpp_build_opts {
   int32_t keep_rounding;  /* 0: a bucket of B records keeps ceil(alpha*B/iProbes) (default);
                              1: floor(...). alpha is taken to 6 decimals.                       */
   int32_t tables_per_pass;/* tables hashed and sorted per pass (0 = chosen from free memory)    */
+  int32_t kappa;          /* limit scaling (Section 3.4, heuristic 2): a bucket keeps
+                             min(B, max(kappa, keep(B))) records; 0 = off (default)             */
+  int32_t center;         /* centering (Section 3.4, heuristic 1): 1 = hash x - c at build, with
+                             c the mean of X (per coordinate: float64 sum in row order, divided by
+                             n in float64, rounded to float32); queries are hashed as given and
+                             scores stay x^T q on the uncentred X; 0 = off (default)            */
+  int32_t filter;         /* FPP_FILTER_FRACTION (0): the per-bucket top fraction of Algorithm 1;
+                             FPP_FILTER_THRESHOLD (1): the global threshold of the theoretical
+                             LSF comparison (appendix, "Falconn++ vs. theoretical LSF"): a record
+                             is kept when each of its l projections, divided by P, is >= t       */
+  float threshold;        /* t for FPP_FILTER_THRESHOLD; <= 0: t = Phi^-1(1 - alpha^(1/l) / (2D)),
+                             so that a point reaches a given bucket with probability alpha/(2D)^l
+                             for Gaussian projections (Phi^-1 by Wichura's algorithm AS 241)    */
 } fpp_build_opts;
+
+#define FPP_FILTER_FRACTION 0
+#define FPP_FILTER_THRESHOLD 1
 
 void fpp_default_build_opts(fpp_build_opts* opts);
 
@@ -148,11 +164,20 @@ typedef struct fpp_index_info {
   int64_t max_bucket;      /* largest kept bucket                                   */
   int64_t device_bytes;    /* device memory held by the index                       */
   double build_ms;         /* wall time of the build call                           */
+  int32_t kappa;           /* limit scaling of the build (0 = off)                  */
+  int32_t centered;        /* 1 if the build hashed x - c                           */
+  int32_t filter;          /* FPP_FILTER_*                                           */
+  float threshold;         /* FPP_FILTER_THRESHOLD: the float32 bound on |y| the build
+                              compared against (fl32(P * t)); 0 otherwise             */
 } fpp_index_info;
 
 int fpp_index_get_info(const fpp_index* index, fpp_index_info* info);
 /* host int64 [L]: ids stored per table. */
 int fpp_index_table_sizes(const fpp_index* index, int64_t* sizes_out);
+
+/* Standard normal quantile Phi^-1(p) for 0 < p < 1 (NaN otherwise), by Wichura's algorithm
+ * AS 241 (PPND16); the threshold filter derives its bound from alpha with it. Host only. */
+double fpp_normal_quantile(double p);
 
 const char* fpp_last_error(void);   /* message of the last failed call on this thread */
 const char* fpp_version(void);
@@ -232,6 +257,9 @@ int fpp_debug_export_table(const fpp_index* index, int32_t t, uint32_t* offsets_
  * L * D^l), each t * (2D)^l + bucket, in no particular order. */
 int fpp_debug_probes(const fpp_index* index, const float* Q, int64_t m, int32_t qProbes,
                      int64_t* probes_out, void* stream);
+
+/* host float [d]: the centring vector c of a centred index (zeros otherwise). */
+int fpp_debug_center(const fpp_index* index, float* c_out);
 
 /* A low-precision store: store FPP_STORE_BF16 -> device uint16 [n][d]; FPP_STORE_FP8 -> device
  * uint8 [n][d] codes plus device float32 [n] scales (scales_out ignored for BF16). */

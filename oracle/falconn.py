@@ -40,6 +40,10 @@ R6  keep(B) = ceil(A*B / (iProbes * 10^6)) with A = floor(alpha * 10^6 + 1/2), e
 R7  qProbes is the total over all tables; probes are ranked by (score desc, table asc, pos1 asc, pos2 asc).
 R8  Top-k order is (score desc, id asc); short results are padded with (-1, -inf).
 R9  Signs: S_{t,f,r}[j] = -1 iff bit 63 of SplitMix64 at counter ((t*l + f)*3 + r)*P + j is set.
+R15 Centering: c_j = fl32(running float64 sum of x_ij over rows in order / n); the build hashes
+    fl32(x - c); queries are hashed unchanged; scores are x^T q on the uncentred data.
+R16 Global threshold: keep a record when each |y| of its pair is >= fl32(P * t) with
+    t = Phi^-1(1 - alpha^(1/l) / (2D)) (sqrt for l = 2), or a given t.
 
 Parity pinned: every function below is pinned by a test against a closed form,
 an invariant stated by the paper, a special case, or brute-force enumeration.
@@ -167,7 +171,7 @@ def n_buckets(D: int, l: int) -> int:
     return (2 * D) ** l
 
 
-def top_pairs(lists, D: int, K: int):
+def top_pairs(lists, D: int, K: int, with_parts: bool = False):
     """Top-K buckets of every vector under one table (Algorithm 1, first loop; reading R5).
 
     Returns bucket [n][K] int64 and key [n][K] float32, best first.
@@ -179,7 +183,8 @@ def top_pairs(lists, D: int, K: int):
     """
     if len(lists) == 1:
         h = lists[0]
-        return h.code[:, :K].astype(np.int64), h.a[:, :K].copy()
+        out = (h.code[:, :K].astype(np.int64), h.a[:, :K].copy())
+        return out + ((h.a[:, :K].copy(),),) if with_parts else out
     h1, h2 = lists
     Kc = min(K, D)
     n = h1.a.shape[0]
@@ -189,7 +194,12 @@ def top_pairs(lists, D: int, K: int):
     b = b.reshape(n, Kc * Kc)
     # order by (score desc, flat position asc); flat position = i*Kc + j is (i, j) lexicographic
     order = np.argsort(-s, axis=1, kind="stable")[:, :K]
-    return np.take_along_axis(b, order, axis=1), np.take_along_axis(s, order, axis=1)
+    out = (np.take_along_axis(b, order, axis=1), np.take_along_axis(s, order, axis=1))
+    if not with_parts:
+        return out
+    a1 = np.repeat(h1.a[:, :Kc], Kc, axis=1)            # flat (i, j) -> a1[i]
+    a2 = np.tile(h2.a[:, :Kc], (1, Kc))                 # flat (i, j) -> a2[j]
+    return out + ((np.take_along_axis(a1, order, axis=1), np.take_along_axis(a2, order, axis=1)),)
 
 
 def alpha_micro(alpha: float) -> int:
@@ -197,20 +207,51 @@ def alpha_micro(alpha: float) -> int:
     return int(math.floor(float(np.float32(alpha)) * 1e6 + 0.5))
 
 
-def keep_count(B: np.ndarray, alpha: float, iProbes: int, rounding: str = "ceil") -> np.ndarray:
+def keep_count(B: np.ndarray, alpha: float, iProbes: int, rounding: str = "ceil",
+               kappa: int = 0) -> np.ndarray:
     """Reading R6 of 'keep the top-(alpha B / iProbes) points' (Algorithm 1, last line).
 
     keep(B) = ceil(A * B / (iProbes * 10^6)) in exact integers, A = alpha in millionths,
     so a decimal alpha such as 0.3 behaves as written (0.3 * 10 / 3 keeps exactly 1).
+    Limit scaling (Section 3.4, heuristic 2) keeps max(kappa, keep(B)) records, and never more
+    than the bucket holds: min(B, max(kappa, keep(B))).
     """
     A = alpha_micro(alpha)
     den = int(iProbes) * 1_000_000
-    num = np.asarray(B, dtype=np.int64) * A
+    B = np.asarray(B, dtype=np.int64)
+    num = B * A
     if rounding == "ceil":
         out = (num + (den - 1)) // den
     else:
         out = num // den
+    if kappa > 0:
+        out = np.maximum(out, np.minimum(B, kappa))
     return out.astype(np.int64)
+
+
+def center_vector(X: np.ndarray, chunk: int = 1 << 16) -> np.ndarray:
+    """Centre of the data (Section 3.4, heuristic 1): c = sum_i x_i / n (reading R15).
+
+    Per coordinate the float64 sum runs over the rows in order (a running sum), is divided by
+    n in float64 and rounded to float32.
+    """
+    X = np.asarray(X, dtype=np.float32)
+    run = np.zeros((1, X.shape[1]), dtype=np.float64)
+    for r0 in range(0, X.shape[0], chunk):
+        run = np.cumsum(np.vstack([run, X[r0:r0 + chunk].astype(np.float64)]), axis=0)[-1:]
+    return (run[0] / float(X.shape[0])).astype(np.float32)
+
+
+def lsf_threshold(alpha: float, D: int, l: int, P: int) -> np.float32:
+    """Global threshold of the theoretical LSF filter (appendix, Falconn++ vs. theoretical LSF):
+    t with Pr[N(0,1) >= t]^l = alpha / (2D)^l, i.e. t = Phi^-1(1 - alpha^(1/l) / (2D)), on the
+    scale of the unnormalised rotation (a unit vector's projections have standard deviation P):
+    the float32 bound P * t on |y| (reading R16)."""
+    from scipy.stats import norm
+    a = float(np.float32(alpha))
+    p = (a if l == 1 else float(np.sqrt(a))) / (2.0 * D)
+    t = float(norm.isf(p))
+    return np.float32(max(0.0, float(P) * t))
 
 
 @dataclass
@@ -227,39 +268,69 @@ class Index:
     offsets: list = field(default_factory=list)    # per table: int64 [NB + 1]
     ids: list = field(default_factory=list)        # per table: int32 [table size]
     keys: list = field(default_factory=list)       # per table: float32 [table size] (the kept keys)
+    center: np.ndarray | None = None               # centring vector of a centred build
+    threshold: np.float32 | None = None            # bound on |y| of a threshold-filter build
 
 
-def build_table(X, signs_t, D, l, alpha, iProbes, rounding="ceil"):
-    """One hash table: hash, top-iProbes buckets per point, per-bucket filter, CSR."""
+def build_table(X, signs_t, D, l, alpha, iProbes, rounding="ceil", kappa=0, threshold=None):
+    """One hash table: hash, top-iProbes buckets per point, per-bucket filter, CSR.
+
+    threshold (float32 bound on |y|): the global-threshold filter keeps a record when each of
+    its l projections is >= the bound, and every bucket keeps all such records.
+    """
     n = X.shape[0]
     lists = [hash_lists(X, signs_t[f], D) for f in range(l)]
-    bucket, key = top_pairs(lists, D, iProbes)
+    if threshold is None:
+        bucket, key = top_pairs(lists, D, iProbes)
+    else:
+        bucket, key, parts = top_pairs(lists, D, iProbes, with_parts=True)
     K = bucket.shape[1]
     rb = bucket.reshape(-1)
     rk = key.reshape(-1)
     rid = np.repeat(np.arange(n, dtype=np.int64), K)
+    if threshold is not None:
+        ok = np.ones(rb.shape[0], dtype=bool)
+        for part in parts:
+            ok &= part.reshape(-1) >= np.float32(threshold)
+        rb, rk, rid = rb[ok], rk[ok], rid[ok]
     # records ordered by (bucket asc, key desc, id asc)
     order = np.lexsort((rid, -rk, rb))
     rb, rk, rid = rb[order], rk[order], rid[order]
     NB = n_buckets(D, l)
     counts = np.bincount(rb, minlength=NB)
     starts = np.concatenate([[0], np.cumsum(counts)])
-    keep = keep_count(counts, alpha, iProbes, rounding)
+    keep = counts.astype(np.int64) if threshold is not None else keep_count(counts, alpha, iProbes, rounding, kappa)
     offsets = np.concatenate([[0], np.cumsum(keep)]).astype(np.int64)
     rank = np.arange(rb.shape[0]) - starts[rb]
     sel = rank < keep[rb]
     return offsets, rid[sel].astype(np.int32), rk[sel]
 
 
-def build_index(X, L, D, alpha, iProbes, seed, l=2, rounding="ceil") -> Index:
-    """Falconn++ index (Algorithm 1) over L tables of l concatenated cross-polytope hashes."""
+def build_index(X, L, D, alpha, iProbes, seed, l=2, rounding="ceil", kappa=0, center=False,
+                filter="fraction", threshold=0.0) -> Index:
+    """Falconn++ index (Algorithm 1) over L tables of l concatenated cross-polytope hashes.
+
+    kappa > 0: limit scaling; center: hash x - c (queries are hashed as given, since
+    argmax x^T q = argmax (x - c)^T q, Section 3.4); filter "threshold": the global threshold
+    of the theoretical LSF comparison, with threshold t > 0 given or derived from alpha.
+    """
     X = np.ascontiguousarray(X, dtype=np.float32)
     n, d = X.shape
     P = padded_dim(d, D)
     S = rotation_signs(seed, L, l, P)
     idx = Index(X=X, L=L, D=D, l=l, P=P, alpha=alpha, iProbes=iProbes, seed=seed, signs=S)
+    Xh = X
+    if center:
+        idx.center = center_vector(X)
+        Xh = (X - idx.center[None, :]).astype(np.float32)
+    T = None
+    if filter == "threshold":
+        T = (np.float32(max(0.0, float(P) * float(np.float32(threshold)))) if threshold > 0
+             else lsf_threshold(alpha, D, l, P))
+        idx.threshold = T
     for t in range(L):
-        off, ids, keys = build_table(X, S[t], D, l, alpha, iProbes, rounding)
+        off, ids, keys = build_table(Xh, S[t], D, l, alpha, iProbes, rounding,
+                                     0 if T is not None else kappa, T)
         idx.offsets.append(off)
         idx.ids.append(ids)
         idx.keys.append(keys)

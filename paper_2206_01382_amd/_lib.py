@@ -29,8 +29,14 @@ STORES = {"fp32": FPP_STORE_FP32, "bf16": FPP_STORE_BF16, "fp8": FPP_STORE_FP8}
 c_i32, c_i64, c_u64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
 
 
+FPP_FILTER_FRACTION = 0
+FPP_FILTER_THRESHOLD = 1
+FILTERS = {"fraction": FPP_FILTER_FRACTION, "threshold": FPP_FILTER_THRESHOLD}
+
+
 class fpp_build_opts(ctypes.Structure):
-    _fields_ = [("l", c_i32), ("stores", c_i32), ("keep_rounding", c_i32), ("tables_per_pass", c_i32)]
+    _fields_ = [("l", c_i32), ("stores", c_i32), ("keep_rounding", c_i32), ("tables_per_pass", c_i32),
+                ("kappa", c_i32), ("center", c_i32), ("filter", c_i32), ("threshold", c_f32)]
 
 
 class fpp_query_opts(ctypes.Structure):
@@ -41,7 +47,8 @@ class fpp_index_info(ctypes.Structure):
     _fields_ = [("n", c_i64), ("d", c_i32), ("L", c_i32), ("D", c_i32), ("l", c_i32), ("P", c_i32),
                 ("iProbes", c_i32), ("stores", c_i32), ("alpha", c_f32), ("seed", c_u64),
                 ("buckets_per_table", c_i64), ("total_ids", c_i64), ("max_bucket", c_i64),
-                ("device_bytes", c_i64), ("build_ms", ctypes.c_double)]
+                ("device_bytes", c_i64), ("build_ms", ctypes.c_double), ("kappa", c_i32),
+                ("centered", c_i32), ("filter", c_i32), ("threshold", c_f32)]
 
 
 class fpp_server_opts(ctypes.Structure):
@@ -84,6 +91,8 @@ SIGNATURES = {
     "fpp_debug_export_table": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "fpp_debug_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp]),
     "fpp_debug_export_store": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "fpp_debug_center": (c_i32, [c_vp, c_vp]),
+    "fpp_normal_quantile": (ctypes.c_double, [ctypes.c_double]),
 }
 
 _LIB = None
@@ -139,11 +148,14 @@ def _stream(stream):
 
 # ------------------------------------------------------------------------------------------------
 def fpp_build_index(X, L: int, D: int, alpha: float, iProbes: int, seed: int, *, l: int = 2,
-                    stores=(), keep_rounding: int = 0, tables_per_pass: int = 0, stream=None) -> c_vp:
+                    stores=(), keep_rounding: int = 0, tables_per_pass: int = 0, kappa: int = 0,
+                    center: bool = False, filter: str = "fraction", threshold: float = 0.0,
+                    stream=None) -> c_vp:
     """Build an index over X (GPU float32 [n][d]); returns the opaque handle."""
     torch = _torch()
     xp = _dev(X, torch.float32, "X")
-    o = fpp_build_opts(l, sum(1 << STORES[s] for s in stores), keep_rounding, tables_per_pass)
+    o = fpp_build_opts(l, sum(1 << STORES[s] for s in stores), keep_rounding, tables_per_pass,
+                       kappa, int(bool(center)), FILTERS[filter], threshold)
     h = c_vp()
     _check(lib().fpp_build_index_ex(xp, X.shape[0], X.shape[1], L, D, alpha, iProbes, seed & (2 ** 64 - 1),
                                     ctypes.byref(o), _stream(stream), ctypes.byref(h)))
@@ -245,6 +257,18 @@ def fpp_debug_query_lists(h, V, stream=None):
     _check(lib().fpp_debug_query_lists(h, _dev(V, torch.float32, "V"), m, c_vp(a.data_ptr()),
                                        c_vp(c.data_ptr()), _stream(stream)))
     return a, c
+
+
+def fpp_debug_center(h) -> np.ndarray:
+    """The centring vector of a centred index (zeros otherwise), float32 [d]."""
+    inf = fpp_index_get_info(h)
+    c = np.zeros(inf["d"], dtype=np.float32)
+    _check(lib().fpp_debug_center(h, c.ctypes.data_as(c_vp)))
+    return c
+
+
+def fpp_normal_quantile(p: float) -> float:
+    return float(lib().fpp_normal_quantile(float(p)))
 
 
 def fpp_debug_build_records(h, t: int, device="cuda", stream=None):

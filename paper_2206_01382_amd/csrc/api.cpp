@@ -55,6 +55,72 @@ int64_t keep_count_host(int64_t B, int64_t A, int K, int rounding) {
   return (int64_t)(rounding == 0 ? (num + den - 1) / den : num / den);
 }
 
+// Standard normal quantile by Wichura's algorithm AS 241 (PPND16, Applied Statistics 37(3),
+// 1988): rational approximations in three ranges, relative accuracy about 1e-16.
+double normal_quantile(double p) {
+  if (!(p > 0.0 && p < 1.0)) return std::nan("");
+  const double q = p - 0.5;
+  if (std::fabs(q) <= 0.425) {
+    const double r = 0.180625 - q * q;
+    const double num = (((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r +
+                             6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r +
+                           1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
+                         1.3314166789178437745e+2) * r + 3.3871328727963666080e+0);
+    const double den = (((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r +
+                             3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r +
+                           5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
+                         4.2313330701600911252e+1) * r + 1.0);
+    return q * num / den;
+  }
+  double r = q < 0.0 ? p : 1.0 - p;
+  r = std::sqrt(-std::log(r));
+  double val;
+  if (r <= 5.0) {
+    r -= 1.6;
+    const double num = (((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r +
+                             2.41780725177450611770e-1) * r + 1.27045825245236838258e+0) * r +
+                           3.64784832476320460504e+0) * r + 5.76949722146069140550e+0) * r +
+                         4.63033784615654529590e+0) * r + 1.42343711074968357734e+0);
+    const double den = (((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r +
+                             1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r +
+                           6.89767334985100004550e-1) * r + 1.67638483018380384940e+0) * r +
+                         2.05319162663775882187e+0) * r + 1.0);
+    val = num / den;
+  } else {
+    r -= 5.0;
+    const double num = (((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r +
+                             1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r +
+                           2.96560571828504891230e-1) * r + 1.78482653991729133580e+0) * r +
+                         5.46378491116411436990e+0) * r + 6.65790464350110377720e+0);
+    const double den = (((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r +
+                             1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r +
+                           1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
+                         5.99832206555887937690e-1) * r + 1.0);
+    val = num / den;
+  }
+  return q < 0.0 ? -val : val;
+}
+
+// Centring vector: per coordinate the float64 sum of the n values in row order, divided by n in
+// float64 and rounded to float32. X is read back in chunks of rows.
+static int compute_center(const float* X, int64_t n, int32_t d, hipStream_t s, std::vector<float>* c) {
+  std::vector<double> acc((size_t)d, 0.0);
+  const int64_t rows = std::max<int64_t>(1, ((int64_t)64 << 20) / ((int64_t)d * 4));
+  std::vector<float> buf((size_t)std::min(rows, n) * d);
+  for (int64_t r0 = 0; r0 < n; r0 += rows) {
+    const int64_t nr = std::min(rows, n - r0);
+    FPP_HIP(hipMemcpyAsync(buf.data(), X + r0 * d, (size_t)nr * d * 4, hipMemcpyDeviceToHost, s));
+    FPP_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < nr; ++i) {
+      const float* row = buf.data() + (size_t)i * d;
+      for (int32_t j = 0; j < d; ++j) acc[j] += (double)row[j];
+    }
+  }
+  c->resize((size_t)d);
+  for (int32_t j = 0; j < d; ++j) (*c)[j] = (float)(acc[j] / (double)n);
+  return FPP_OK;
+}
+
 static int next_pow2(int v) {
   int p = 1;
   while (p < v) p <<= 1;
@@ -75,7 +141,8 @@ static int dalloc(T** p, size_t count, int64_t* acc) {
 
 static void free_index_memory(fpp_index* ix) {
   if (!ix) return;
-  void* ptrs[] = {ix->X, ix->Xbf16, ix->Xfp8, ix->fp8_scale, ix->sign_mask, ix->offsets, ix->ids};
+  void* ptrs[] = {ix->X, ix->Xbf16, ix->Xfp8, ix->fp8_scale, ix->sign_mask, ix->offsets, ix->ids,
+                  ix->center_vec};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -139,6 +206,12 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   if (o.keep_rounding != 0 && o.keep_rounding != 1) return set_error("keep_rounding must be 0 or 1"), FPP_EINVAL;
   if (o.stores & ~((1 << FPP_STORE_BF16) | (1 << FPP_STORE_FP8)))
     return set_error("unknown store bits 0x%x", o.stores), FPP_EINVAL;
+  if (o.kappa < 0) return set_error("kappa=%d < 0", o.kappa), FPP_EINVAL;
+  if (o.center != 0 && o.center != 1) return set_error("center must be 0 or 1"), FPP_EINVAL;
+  if (o.filter != FPP_FILTER_FRACTION && o.filter != FPP_FILTER_THRESHOLD)
+    return set_error("unknown filter %d", o.filter), FPP_EINVAL;
+  if (!(o.threshold == o.threshold) || std::isinf(o.threshold))
+    return set_error("threshold is not finite"), FPP_EINVAL;
 
   std::unique_ptr<fpp_index> ix(new (std::nothrow) fpp_index());
   if (!ix) return set_error("host allocation failed"), FPP_ENOMEM;
@@ -162,6 +235,9 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   ix->alpha_micro = (int64_t)std::floor((double)alpha * 1e6 + 0.5);
   ix->seed = seed;
   ix->keep_rounding = o.keep_rounding;
+  ix->kappa = o.filter == FPP_FILTER_FRACTION ? o.kappa : 0;
+  ix->centered = o.center;
+  ix->filter = o.filter;
   ix->stores = o.stores;
   ix->NB = o.l == 1 ? 2LL * D : 4LL * D * D;
   ix->ldx = (d + 3) / 4 * 4;
@@ -171,8 +247,19 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   const int K = iProbes;
   const int64_t nK = n * K;
 
+  if (ix->filter == FPP_FILTER_THRESHOLD) {
+    // t from alpha: a point reaches a given bucket with probability alpha / (2D)^l when each of
+    // its l projections, divided by P (the scale of the unnormalised rotation), is >= t
+    const double pa = (o.l == 1 ? (double)alpha : std::sqrt((double)alpha)) / (2.0 * D);
+    const double t = o.threshold > 0.f ? (double)o.threshold : -normal_quantile(pa);
+    ix->thr = (float)((double)ix->P * t);
+    if (!(ix->thr >= 0.f)) ix->thr = 0.f;
+  }
   // upper bound of the stored ids: sum over buckets of keep(B) <= alpha * n + #non-empty buckets
-  const int64_t per_table = keep_count_host(nK, ix->alpha_micro, K, 0) + std::min<int64_t>(NB, nK) + 1;
+  // (plus kappa per non-empty bucket under limit scaling; every record under the threshold)
+  int64_t per_table = keep_count_host(nK, ix->alpha_micro, K, 0) +
+                      (int64_t)(1 + ix->kappa) * std::min<int64_t>(NB, nK) + 1;
+  if (ix->filter == FPP_FILTER_THRESHOLD || per_table > nK + 1) per_table = nK + 1;
   const int64_t id_cap = per_table * L;
   if (id_cap >= (int64_t)1 << 32) return set_error("more than 2^32 - 1 stored ids"), FPP_ECAPACITY;
 
@@ -181,6 +268,18 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   FPP_HIP(hipMemsetAsync(ix->X, 0, (size_t)n * ix->ldx * 4, s));
   FPP_HIP(hipMemcpy2DAsync(ix->X, (size_t)ix->ldx * 4, X, (size_t)d * 4, (size_t)d * 4, (size_t)n,
                            hipMemcpyDeviceToDevice, s));
+  DeviceScratch centred;
+  ix->Xh = ix->X;
+  if (ix->centered) {
+    std::vector<float> c;
+    FPP_TRY(compute_center(X, n, d, s, &c));
+    FPP_TRY(dalloc(&ix->center_vec, (size_t)d, &bytes));
+    FPP_HIP(hipMemcpyAsync(ix->center_vec, c.data(), (size_t)d * 4, hipMemcpyHostToDevice, s));
+    float* Xc = nullptr;
+    FPP_TRY(centred.get(&Xc, (size_t)n * ix->ldx));
+    FPP_HIP(launch_center(ix.get(), Xc, s));
+    ix->Xh = Xc;
+  }
   const std::vector<uint32_t> masks = make_sign_masks(seed, L, o.l, ix->P);
   FPP_TRY(dalloc(&ix->sign_mask, masks.size(), &bytes));
   FPP_HIP(hipMemcpyAsync(ix->sign_mask, masks.data(), masks.size() * 4, hipMemcpyHostToDevice, s));
@@ -232,6 +331,7 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   if (o.stores) FPP_HIP(launch_quantize(ix.get(), s));
   FPP_HIP(hipStreamSynchronize(s));
   ix->device_bytes = bytes;
+  ix->Xh = nullptr;   // the centred copy is released with this call's scratch
   ix->build_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   guard.armed = false;
@@ -464,6 +564,10 @@ void fpp_default_build_opts(fpp_build_opts* o) {
   o->stores = 0;
   o->keep_rounding = 0;
   o->tables_per_pass = 0;
+  o->kappa = 0;
+  o->center = 0;
+  o->filter = FPP_FILTER_FRACTION;
+  o->threshold = 0.f;
 }
 
 void fpp_default_query_opts(fpp_query_opts* o) {
@@ -565,6 +669,10 @@ int fpp_index_get_info(const fpp_index* ix, fpp_index_info* info) {
   info->max_bucket = ix->max_bucket;
   info->device_bytes = ix->device_bytes;
   info->build_ms = ix->build_ms;
+  info->kappa = ix->kappa;
+  info->centered = ix->centered;
+  info->filter = ix->filter;
+  info->threshold = ix->filter == FPP_FILTER_THRESHOLD ? ix->thr : 0.f;
   return FPP_OK;
 }
 
@@ -605,9 +713,35 @@ int fpp_debug_build_records(const fpp_index* ix, int32_t t, uint32_t* bucket_out
                             void* stream) {
   if (!ix || !bucket_out || !key_out) return set_error("NULL argument"), FPP_EINVAL;
   if (t < 0 || t >= ix->L) return set_error("table %d out of range", t), FPP_EINVAL;
-  FPP_HIP(launch_hash_build(ix, t, 1, bucket_out, key_out, (hipStream_t)stream));
+  hipStream_t s = (hipStream_t)stream;
+  if (!ix->centered) {
+    FPP_HIP(launch_hash_build(ix, t, 1, bucket_out, key_out, s));
+    return FPP_OK;
+  }
+  // a centred index hashed X - c: rebuild that copy for the call
+  DeviceScratch sc;
+  float* Xc = nullptr;
+  FPP_TRY(sc.get(&Xc, (size_t)ix->n * ix->ldx));
+  FPP_HIP(launch_center(ix, Xc, s));
+  fpp_index view = *ix;
+  view.Xh = Xc;
+  FPP_HIP(launch_hash_build(&view, t, 1, bucket_out, key_out, s));
+  FPP_HIP(hipStreamSynchronize(s));
+  view.table_base.clear();
   return FPP_OK;
 }
+
+int fpp_debug_center(const fpp_index* ix, float* c_out) {
+  if (!ix || !c_out) return set_error("NULL argument"), FPP_EINVAL;
+  if (!ix->center_vec) {
+    std::fill(c_out, c_out + ix->d, 0.f);
+    return FPP_OK;
+  }
+  FPP_HIP(hipMemcpy(c_out, ix->center_vec, (size_t)ix->d * 4, hipMemcpyDeviceToHost));
+  return FPP_OK;
+}
+
+double fpp_normal_quantile(double p) { return normal_quantile(p); }
 
 int fpp_debug_export_table(const fpp_index* ix, int32_t t, uint32_t* offsets_out, int32_t* ids_out) {
   if (!ix || !offsets_out || !ids_out) return set_error("NULL argument"), FPP_EINVAL;

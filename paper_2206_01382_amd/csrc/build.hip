@@ -13,7 +13,9 @@
 //               scan) by a workgroup that bitonic-sorts them in LDS; the result does not depend on
 //               the scatter order;
 //   6. absolute CSR offsets += table start.
-// keep(B) = ceil(A * B / (iProbes * 10^6)) (or floor) with A = alpha in millionths.
+// keep(B) = ceil(A * B / (iProbes * 10^6)) (or floor) with A = alpha in millionths, at least
+// min(B, kappa) under limit scaling; under the global-threshold filter the hash kernel has already
+// dropped the records below the threshold and every bucket keeps all of its records.
 #include "fpp_internal.hpp"
 
 namespace fpp {
@@ -21,10 +23,15 @@ namespace {
 
 constexpr int kScanThreads = 1024;
 
-__device__ __forceinline__ uint32_t keep_of(uint32_t B, int64_t A, int K, int rounding) {
+// Records a bucket of B keeps: all of them under the global-threshold filter (A < 0), else the
+// alpha fraction keep(B), raised to min(B, kappa) by limit scaling (Section 3.4, heuristic 2).
+__device__ __forceinline__ uint32_t keep_of(uint32_t B, int64_t A, int K, int rounding, int kappa) {
+  if (A < 0) return B;
   const uint64_t den = (uint64_t)K * 1000000ull;
   const uint64_t num = (uint64_t)B * (uint64_t)A;
-  return (uint32_t)(rounding == 0 ? (num + den - 1) / den : num / den);
+  const uint32_t kp = (uint32_t)(rounding == 0 ? (num + den - 1) / den : num / den);
+  const uint32_t lim = B < (uint32_t)kappa ? B : (uint32_t)kappa;
+  return kp > lim ? kp : lim;
 }
 
 __global__ __launch_bounds__(256) void count_kernel(const uint32_t* __restrict__ rec_bucket,
@@ -34,6 +41,7 @@ __global__ __launch_bounds__(256) void count_kernel(const uint32_t* __restrict__
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= nK) return;
   const uint32_t b = rec_bucket[(size_t)tt * nK + r];
+  if (b == kDropped) return;
   atomicAdd(&cnt[(size_t)tt * NB + b], 1u);
 }
 
@@ -81,7 +89,7 @@ constexpr int kLdsSortMax = 8192;         // larger buckets are ranked by counti
 
 // One block per table of the chunk.
 __global__ __launch_bounds__(kScanThreads) void scan_kernel(
-    const uint32_t* __restrict__ cnt, int64_t NB, int64_t A, int K, int rounding,
+    const uint32_t* __restrict__ cnt, int64_t NB, int64_t A, int K, int rounding, int kappa,
     uint32_t* __restrict__ start, uint32_t* __restrict__ offsets_chunk,
     uint64_t* __restrict__ meta, uint64_t* __restrict__ large, uint32_t* __restrict__ n_large) {
   __shared__ uint32_t sa[kScanThreads / 64 + 1], sb[kScanThreads / 64 + 1];
@@ -95,7 +103,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(
   uint32_t sc = 0, sk = 0, mk = 0;
   for (int64_t b = b0; b < b1; ++b) {
     const uint32_t B = c[b];
-    const uint32_t kp = keep_of(B, A, K, rounding);
+    const uint32_t kp = keep_of(B, A, K, rounding, kappa);
     sc += B;
     sk += kp;
     mk = kp > mk ? kp : mk;
@@ -104,7 +112,7 @@ __global__ __launch_bounds__(kScanThreads) void scan_kernel(
   block_scan2(sc, sk, tc, tk, sa, sb);
   for (int64_t b = b0; b < b1; ++b) {
     const uint32_t B = c[b];
-    const uint32_t kp = keep_of(B, A, K, rounding);
+    const uint32_t kp = keep_of(B, A, K, rounding, kappa);
     st[b] = sc;
     of[b] = sk;
     sc += B;
@@ -141,6 +149,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(
   if (r >= nK) return;
   const size_t o = (size_t)tt * nK;
   const uint32_t b = rec_bucket[o + r];
+  if (b == kDropped) return;
   const uint32_t pos = start[(size_t)tt * (NB + 1) + b] + atomicAdd(&fill[(size_t)tt * NB + b], 1u);
   srt_key[o + pos] = rec_key[o + r];
   srt_id[o + pos] = (int32_t)(r / K);
@@ -270,7 +279,8 @@ hipError_t launch_build_tables(const fpp_index* ix, int t0, int Tc, const BuildS
   hipLaunchKernelGGL(count_kernel, grid_r, dim3(256), 0, s, bs.rec_bucket, nK, NB, bs.cnt);
   if ((e = hipMemsetAsync(bs.n_large, 0, sizeof(uint32_t), s)) != hipSuccess) return e;
   hipLaunchKernelGGL(scan_kernel, dim3(Tc), dim3(kScanThreads), 0, s, bs.cnt, NB,
-                     (int64_t)ix->alpha_micro, K, ix->keep_rounding, bs.start, offc, bs.meta,
+                     ix->filter == FPP_FILTER_THRESHOLD ? (int64_t)-1 : (int64_t)ix->alpha_micro, K,
+                     ix->keep_rounding, ix->kappa, bs.start, offc, bs.meta,
                      bs.large, bs.n_large);
   hipLaunchKernelGGL(bases_kernel, dim3(1), dim3(64), 0, s, t0, Tc, bs.meta, bs.tbase);
   hipLaunchKernelGGL(scatter_kernel, grid_r, dim3(256), 0, s, bs.rec_bucket, bs.rec_key, nK, K, NB,

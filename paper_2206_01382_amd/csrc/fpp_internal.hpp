@@ -34,6 +34,7 @@ constexpr int kMaxIProbes = 16;      // build kernel keeps at most this many buc
 constexpr int kMaxK = 512;           // results / short list per query
 constexpr int kMaxD = 1024;          // dimension of stored vectors
 constexpr int kMaxP = 4096;          // rotation length
+constexpr uint32_t kDropped = 0xffffffffu;   // bucket of a build record the threshold filter drops
 
 // ----------------------------------------------------------------------------------------------
 // The index object (opaque in the ABI).
@@ -47,6 +48,10 @@ struct fpp_index {
   int64_t alpha_micro = 0;   // alpha in millionths
   uint64_t seed = 0;
   int32_t keep_rounding = 0;
+  int32_t kappa = 0;         // limit scaling: keep min(B, max(kappa, keep(B)))
+  int32_t centered = 0;
+  int32_t filter = 0;        // FPP_FILTER_*
+  float thr = 0.f;           // FPP_FILTER_THRESHOLD: keep a record when every |y| >= thr
   int32_t stores = 0;        // bit mask of low-precision stores
   int64_t NB = 0;            // buckets per table, (2D)^l
   int32_t ldx = 0;           // FP32 row stride in floats (multiple of 4)
@@ -58,6 +63,8 @@ struct fpp_index {
   uint16_t* Xbf16 = nullptr;      // device [n][ld16]
   uint8_t* Xfp8 = nullptr;        // device [n][ld8]
   float* fp8_scale = nullptr;     // device [n]
+  float* center_vec = nullptr;    // device [d] centring vector (centred builds only)
+  const float* Xh = nullptr;      // hashing input of the build kernels ([n][ldx]): X, or X - c
   uint32_t* sign_mask = nullptr;  // device [L][l][3][P]: 0 or 0x80000000 (xor mask of the sign)
   uint32_t* offsets = nullptr;    // device [L][NB + 1], absolute positions into ids
   int32_t* ids = nullptr;         // device [total_ids]
@@ -110,6 +117,10 @@ hipError_t launch_build_tables(const fpp_index* ix, int t0, int Tc, const BuildS
 
 // Quantised stores.
 hipError_t launch_quantize(const fpp_index* ix, hipStream_t s);
+// Centred copy of X (ix->center_vec must be set): Xc [n][ldx].
+hipError_t launch_center(const fpp_index* ix, float* Xc, hipStream_t s);
+// Standard normal quantile (Wichura's algorithm AS 241, PPND16), 0 < p < 1.
+double normal_quantile(double p);
 
 // Probe selection: probes [m][qcap] as absolute offset-array positions t * (NB + 1) + bucket;
 // nprobe[m] receives the count per query.

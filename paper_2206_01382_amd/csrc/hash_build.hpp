@@ -119,9 +119,11 @@ __device__ __forceinline__ void toplist_group_merge(TopList<KMAX>& t) {
 
 // l = 2: rank every candidate pair (i, j) with (i+1)(j+1) <= K among the candidates by
 // (score desc, i asc, j asc) and write the K best at the slot given by their rank.
+// thr >= 0 (global-threshold filter): a pair whose |y1| or |y2| is below thr is written with the
+// bucket kDropped, which the table build skips.
 template <int KMAX>
 __device__ __forceinline__ void select_pairs(const TopList<KMAX>& A, const TopList<KMAX>& B, int K,
-                                             int D, uint32_t* rb, float* rk) {
+                                             int D, float thr, uint32_t* rb, float* rk) {
   const int lim = K < D ? K : D;
   constexpr bool kUnroll = KMAX <= 8;
   if constexpr (kUnroll) {
@@ -143,7 +145,8 @@ __device__ __forceinline__ void select_pairs(const TopList<KMAX>& A, const TopLi
             }
           }
           if (rank < K) {
-            rb[rank] = (uint32_t)(A.code[i] * (2 * D) + B.code[j]);
+            const bool keep = !(A.a[i] < thr) && !(B.a[j] < thr);
+            rb[rank] = keep ? (uint32_t)(A.code[i] * (2 * D) + B.code[j]) : kDropped;
             rk[rank] = s;
           }
         }
@@ -161,7 +164,8 @@ __device__ __forceinline__ void select_pairs(const TopList<KMAX>& A, const TopLi
           }
         }
         if (rank < K) {
-          rb[rank] = (uint32_t)(A.code[i] * (2 * D) + B.code[j]);
+          const bool keep = !(A.a[i] < thr) && !(B.a[j] < thr);
+          rb[rank] = keep ? (uint32_t)(A.code[i] * (2 * D) + B.code[j]) : kDropped;
           rk[rank] = s;
         }
       }
@@ -172,7 +176,7 @@ __device__ __forceinline__ void select_pairs(const TopList<KMAX>& A, const TopLi
 template <int P, int G, int KMAX>
 __global__ __launch_bounds__(64) void hash_build_kernel(
     const float* __restrict__ X, int64_t n, int d, int ldx, const uint32_t* __restrict__ sign_mask,
-    int t0, int Tc, int l, int D, int K, uint32_t* __restrict__ rec_bucket,
+    int t0, int Tc, int l, int D, int K, float thr, uint32_t* __restrict__ rec_bucket,
     float* __restrict__ rec_key) {
   constexpr int E = P / G;          // elements per lane
   constexpr int PPB = 64 / G;       // points per block
@@ -247,11 +251,11 @@ __global__ __launch_bounds__(64) void hash_build_kernel(
 #pragma unroll
       for (int s = 0; s < KMAX; ++s)
         if (s < K) {
-          rb[s] = (uint32_t)list0.code[s];
+          rb[s] = !(list0.a[s] < thr) ? (uint32_t)list0.code[s] : kDropped;
           rk[s] = list0.a[s];
         }
     } else {
-      select_pairs<KMAX>(list0, list1, K, D, rb, rk);
+      select_pairs<KMAX>(list0, list1, K, D, thr, rb, rk);
     }
   }
 }
@@ -263,8 +267,8 @@ inline hipError_t launch_build_p(const fpp_index* ix, int t0, int Tc, uint32_t* 
   const int64_t blocks = (ix->n + PPB - 1) / PPB;
   const size_t lds = (size_t)ix->d * (PPB + 1) * sizeof(float);
   hipLaunchKernelGGL((hash_build_kernel<P, G, KMAX>), dim3((unsigned)blocks), dim3(64), lds, s,
-                     ix->X, ix->n, ix->d, ix->ldx, ix->sign_mask, t0, Tc, ix->l, ix->D,
-                     ix->iProbes, rb, rk);
+                     ix->Xh ? ix->Xh : ix->X, ix->n, ix->d, ix->ldx, ix->sign_mask, t0, Tc, ix->l,
+                     ix->D, ix->iProbes, ix->filter == FPP_FILTER_THRESHOLD ? ix->thr : -1.0f, rb, rk);
   return hipGetLastError();
 }
 

@@ -65,7 +65,25 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const float* __restrict_
   if (lane == 0) scale[r] = s;
 }
 
+// Centred copy for the build's hashing: xc[i][j] = fl32(x[i][j] - c[j]) for j < d, 0 in the row
+// padding (Section 3.4, heuristic 1).
+__global__ __launch_bounds__(256) void center_kernel(const float* __restrict__ X, int64_t n, int d,
+                                                     int ldx, const float* __restrict__ c,
+                                                     float* __restrict__ Xc) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * ldx) return;
+  const int j = (int)(i % ldx);
+  Xc[i] = j < d ? X[i] - c[j] : 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_center(const fpp_index* ix, float* Xc, hipStream_t s) {
+  const int64_t tot = ix->n * ix->ldx;
+  hipLaunchKernelGGL(center_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, ix->X,
+                     ix->n, ix->d, ix->ldx, ix->center_vec, Xc);
+  return hipGetLastError();
+}
 
 hipError_t launch_quantize(const fpp_index* ix, hipStream_t s) {
   if (ix->Xbf16) {

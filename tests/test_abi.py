@@ -106,3 +106,31 @@ def test_query_null_index_rejected():
     assert L.fpp_query_workspace_bytes(None, 1, 1, 1, None) == -1
     L.fpp_free_index(None)          # ignored
     L.fpp_server_destroy(None)      # ignored
+
+
+def test_normal_quantile_matches_scipy(so):
+    """The library's AS 241 quantile (used by the threshold filter) against scipy's ndtri."""
+    from scipy.special import ndtri
+    so.fpp_normal_quantile.restype = ctypes.c_double
+    so.fpp_normal_quantile.argtypes = [ctypes.c_double]
+    for p in (1e-300, 1e-50, 1e-12, 1e-6, 2.2e-3, 0.02425, 0.075, 0.3, 0.5, 0.7, 0.975, 1 - 1e-9):
+        got, want = so.fpp_normal_quantile(p), float(ndtri(p))
+        assert abs(got - want) <= 1e-14 * max(1.0, abs(want)), (p, got, want)
+    assert so.fpp_normal_quantile(0.5) == 0.0
+    assert so.fpp_normal_quantile(0.0) != so.fpp_normal_quantile(0.0)   # NaN outside (0, 1)
+
+
+def test_build_option_validation():
+    import paper_2206_01382_amd._lib as L
+    lib = L.lib()
+    o = L.fpp_build_opts()
+    lib.fpp_default_build_opts(ctypes.byref(o))
+    assert (o.kappa, o.center, o.filter, o.threshold) == (0, 0, L.FPP_FILTER_FRACTION, 0.0)
+    h = ctypes.c_void_p()
+    for field, val in (("kappa", -1), ("center", 2), ("filter", 7), ("threshold", float("inf"))):
+        bad = L.fpp_build_opts()
+        lib.fpp_default_build_opts(ctypes.byref(bad))
+        setattr(bad, field, val)
+        rc = lib.fpp_build_index_ex(ctypes.c_void_p(16), 100, 8, 2, 8, 0.5, 1, 1, ctypes.byref(bad),
+                                    None, ctypes.byref(h))
+        assert rc == L.FPP_EINVAL, field

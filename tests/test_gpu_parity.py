@@ -440,6 +440,53 @@ def test_empty_query_batch_and_errors():
 
 
 # ----------------------------------------------------------------------------------------------
+# limit scaling, centering and the global-threshold filter
+HEUR = {
+    "kappa5": dict(kappa=5),
+    "center": dict(center=True),
+    "center_kappa3": dict(center=True, kappa=3),
+    "lsf_derived_t": dict(filter="threshold"),
+    "lsf_given_t": dict(filter="threshold", threshold=0.9),
+    "lsf_center_l1": dict(filter="threshold", center=True, l=1),
+}
+
+
+@pytest.mark.parametrize("name", list(HEUR))
+def test_heuristic_builds_bit_exact(name):
+    opts = dict(HEUR[name])
+    l = opts.pop("l", 2)
+    X, Q = synthdata.clustered_sphere(6_000, 64, 30, 12, 0.4, seed=31)
+    X = (X + np.float32(0.15)).astype(np.float32)          # off-centre, so that c matters
+    L, D, alpha, K = 3, 16, 0.3, 3
+    oi = O.build_index(X, L, D, alpha, K, SEED, l=l, **opts)
+    Xd = torch.from_numpy(X).cuda()
+    h = F().fpp_build_index(Xd, L, D, alpha, K, SEED, l=l, **opts)
+    try:
+        inf = F().fpp_index_get_info(h)
+        assert inf["kappa"] == (0 if opts.get("filter") == "threshold" else opts.get("kappa", 0))
+        assert inf["centered"] == int(opts.get("center", False))
+        if opts.get("filter") == "threshold":
+            assert np.float32(inf["threshold"]) == oi.threshold
+        c = F().fpp_debug_center(h)
+        np.testing.assert_array_equal(c, oi.center if oi.center is not None else np.zeros(64, np.float32))
+        for t in range(L):
+            off, ids = F().fpp_debug_export_table(h, t)
+            np.testing.assert_array_equal(off, oi.offsets[t])
+            np.testing.assert_array_equal(ids, oi.ids[t])
+        if opts.get("center") and opts.get("filter") != "threshold":
+            b, k = F().fpp_debug_build_records(h, 1)
+            lists = [O.hash_lists((X - oi.center).astype(np.float32), oi.signs[1, f], D) for f in range(l)]
+            ob, ok = O.top_pairs(lists, D, K)
+            np.testing.assert_array_equal(b.cpu().numpy().astype(np.int64), ob)
+        Qd = torch.from_numpy(Q).cuda()
+        ids, sc = F().fpp_query(h, Qd, 10, 8 * L)
+        oids, osc, _ = O.query(oi, Q, 10, 8 * L)
+        assert check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 64) <= 3
+    finally:
+        F().fpp_free_index(h)
+
+
+# ----------------------------------------------------------------------------------------------
 # precision stores
 @pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64"])
 def test_stores_bit_exact(name):

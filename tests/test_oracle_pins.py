@@ -233,6 +233,115 @@ def test_filter_matches_per_bucket_brute_force(alpha, iprobes):
         assert alpha * 400 - 1e-9 <= total <= alpha * 400 + nonempty
 
 
+# ------------------------------------------------------------------ heuristics and the LSF filter
+def test_limit_scaling_keep_values():
+    """max(kappa, keep(B)) records, never more than the bucket holds (Section 3.4, heuristic 2)."""
+    got = O.keep_count(np.array([0, 1, 2, 5, 10, 100]), 0.3, 3, kappa=4)
+    assert got.tolist() == [0, 1, 2, 4, 4, 10]
+    assert O.keep_count(np.array([5, 100]), 0.3, 3, kappa=0).tolist() == [1, 10]
+
+
+def test_limit_scaling_table_matches_per_bucket_brute_force():
+    X = _uniform_data(400, 16, 61)
+    D, K, alpha, kappa = 8, 2, 0.1, 3
+    idx = O.build_index(X, L=1, D=D, alpha=alpha, iProbes=K, seed=5, l=2, kappa=kappa)
+    lists = [O.hash_lists(X, idx.signs[0, f], D) for f in range(2)]
+    b, key = O.top_pairs(lists, D, K)
+    buckets = {}
+    for p in range(400):
+        for r in range(K):
+            buckets.setdefault(int(b[p, r]), []).append((-float(key[p, r]), p))
+    off, ids = idx.offsets[0], idx.ids[0]
+    for bk in range(O.n_buckets(D, 2)):
+        recs = sorted(buckets.get(bk, []))
+        B = len(recs)
+        keep = min(B, max(kappa, math.ceil(round(alpha * 1e6) * B / (K * 1e6) - 1e-12))) if B else 0
+        assert off[bk + 1] - off[bk] == keep
+        assert ids[off[bk]:off[bk + 1]].tolist() == [p for _, p in recs[:keep]]
+
+
+def test_center_vector_is_the_mean():
+    rng = np.random.default_rng(62)
+    X = rng.standard_normal((3000, 7)).astype(np.float32) + np.float32(0.25)
+    c = O.center_vector(X, chunk=1000)
+    for j in range(7):
+        exact = math.fsum(float(v) for v in X[:, j]) / 3000
+        assert abs(float(c[j]) - exact) <= 1.5 * np.spacing(np.float32(abs(exact)))
+    # the running sum in row order, whatever the chunking
+    assert np.array_equal(c, O.center_vector(X, chunk=7))
+
+
+def test_centering_symmetric_data_changes_nothing():
+    """X together with -X has centre 0 exactly, so the centred index is the plain one."""
+    X = _uniform_data(150, 16, 63)
+    X2 = np.concatenate([X, -X])
+    assert not O.center_vector(X2).any()
+    a = O.build_index(X2, L=2, D=8, alpha=0.5, iProbes=2, seed=4, l=2, center=True)
+    b = O.build_index(X2, L=2, D=8, alpha=0.5, iProbes=2, seed=4, l=2)
+    for t in range(2):
+        assert np.array_equal(a.offsets[t], b.offsets[t]) and np.array_equal(a.ids[t], b.ids[t])
+
+
+def test_centering_hashes_x_minus_c_and_keeps_the_argmax():
+    rng = np.random.default_rng(64)
+    X = rng.standard_normal((500, 16))
+    X = (X / np.linalg.norm(X, axis=1, keepdims=True) + 0.5).astype(np.float32)
+    idx = O.build_index(X, L=1, D=8, alpha=1.0, iProbes=1, seed=6, l=1, center=True)
+    c = O.center_vector(X)
+    Xc = (X - c).astype(np.float32)
+    home = O.hash_codes(Xc, idx.signs, 8)[:, 0, 0]
+    off = idx.offsets[0]
+    for bk in np.nonzero(np.diff(off))[0]:
+        assert np.all(home[idx.ids[0][off[bk]:off[bk + 1]]] == bk)
+    # argmax x^T q = argmax (x - c)^T q (Section 3.4): the same top-5 by exact scores
+    q = rng.standard_normal(16)
+    X64, c64 = X.astype(np.float64), c.astype(np.float64)
+    assert np.array_equal(np.argsort(-(X64 @ q))[:5], np.argsort(-((X64 - c64) @ q))[:5])
+
+
+@pytest.mark.parametrize("l", [1, 2])
+def test_lsf_threshold_tail_probability(l):
+    """Pr[N(0,1) >= t]^l = alpha / (2D)^l (checked with math.erfc), on the |y| scale P."""
+    alpha, D, P = 0.1, 16, 32
+    T = O.lsf_threshold(alpha, D, l, P)
+    t = float(T) / P
+    tail = 0.5 * math.erfc(t / math.sqrt(2.0))
+    assert abs(tail ** l - float(np.float32(alpha)) / (2 * D) ** l) <= 1e-6 * float(np.float32(alpha)) / (2 * D) ** l
+
+
+def test_threshold_filter_keeps_records_above_the_bound():
+    X = _uniform_data(300, 16, 65)
+    D, K = 8, 3
+    idx = O.build_index(X, L=1, D=D, alpha=0.2, iProbes=K, seed=7, l=2, filter="threshold", threshold=0.8)
+    T = np.float32(16 * float(np.float32(0.8)))
+    assert idx.threshold == T
+    lists = [O.hash_lists(X, idx.signs[0, f], D) for f in range(2)]
+    b, key = O.top_pairs(lists, D, K)
+    want = {}
+    for p in range(300):
+        for r in range(K):
+            # positions of the pair in the two lists: recover |y1|, |y2| by code
+            c1, c2 = divmod(int(b[p, r]), 2 * D)
+            a1 = lists[0].a[p][list(lists[0].code[p]).index(c1)]
+            a2 = lists[1].a[p][list(lists[1].code[p]).index(c2)]
+            if a1 >= T and a2 >= T:
+                want.setdefault(int(b[p, r]), []).append((-float(key[p, r]), p))
+    off, ids = idx.offsets[0], idx.ids[0]
+    for bk in range(O.n_buckets(D, 2)):
+        recs = sorted(want.get(bk, []))
+        assert ids[off[bk]:off[bk + 1]].tolist() == [p for _, p in recs]
+
+
+def test_threshold_zero_keeps_every_record():
+    """A bound below every projection keeps all records: with iProbes = 1 that is the alpha = 1
+    table (plain cross-polytope LSH)."""
+    X = _uniform_data(300, 16, 66)
+    a = O.build_index(X, L=2, D=8, alpha=0.3, iProbes=1, seed=8, l=2, filter="threshold", threshold=1e-30)
+    b = O.build_index(X, L=2, D=8, alpha=1.0, iProbes=1, seed=8, l=2)
+    for t in range(2):
+        assert np.array_equal(a.offsets[t], b.offsets[t]) and np.array_equal(a.ids[t], b.ids[t])
+
+
 # ------------------------------------------------------------------ query
 def _brute_probes(idx, q, qProbes):
     D, L = idx.D, idx.L
