@@ -75,6 +75,9 @@ typedef struct fpp_build_opts {
 #define FPP_FILTER_FRACTION 0
 #define FPP_FILTER_THRESHOLD 1
 
+#define FPP_PROBE_SUM 0
+#define FPP_PROBE_GAP 1
+
 void fpp_default_build_opts(fpp_build_opts* opts);
 
 /*
@@ -116,6 +119,10 @@ typedef struct fpp_query_opts {
   double* stage_ms;    /* optional host double [4]: milliseconds spent in hashing, probe
                           selection, gather/score/top-k and rerank, from HIP events recorded on
                           `stream` around each kernel; when set, the call synchronises `stream`  */
+  int32_t probe_score; /* FPP_PROBE_SUM (0): a bucket's probe score is the sum of its |projections|
+                          (Section 3.4, Falconn++); FPP_PROBE_GAP (1): that sum minus the best
+                          pair of its table, the multi-probe score of plain Falconn (Section 2.2);
+                          both ranked globally over the L tables                              */
 } fpp_query_opts;
 
 void fpp_default_query_opts(fpp_query_opts* opts);
@@ -196,6 +203,7 @@ typedef struct fpp_server_opts {
   int32_t max_batch;       /* queries packed into one launch, >= 1                              */
   int32_t store;           /* as fpp_query_opts.store                                           */
   int32_t rerank_R;        /* as fpp_query_opts.rerank_R                                        */
+  int32_t probe_score;     /* as fpp_query_opts.probe_score                                     */
 } fpp_server_opts;
 
 void fpp_default_server_opts(fpp_server_opts* opts);
@@ -254,9 +262,10 @@ int fpp_debug_export_table(const fpp_index* index, int32_t t, uint32_t* offsets_
                            int32_t* ids_out);
 
 /* The selected probes of each query: device int64 [m][qProbes'] with qProbes' = min(qProbes,
- * L * D^l), each t * (2D)^l + bucket, in no particular order. */
+ * L * D^l), each t * (2D)^l + bucket, in no particular order; probe_score as in
+ * fpp_query_opts. */
 int fpp_debug_probes(const fpp_index* index, const float* Q, int64_t m, int32_t qProbes,
-                     int64_t* probes_out, void* stream);
+                     int32_t probe_score, int64_t* probes_out, void* stream);
 
 /* host float [d]: the centring vector c of a centred index (zeros otherwise). */
 int fpp_debug_center(const fpp_index* index, float* c_out);

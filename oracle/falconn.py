@@ -44,6 +44,9 @@ R15 Centering: c_j = fl32(running float64 sum of x_ij over rows in order / n); t
     fl32(x - c); queries are hashed unchanged; scores are x^T q on the uncentred data.
 R16 Global threshold: keep a record when each |y| of its pair is >= fl32(P * t) with
     t = Phi^-1(1 - alpha^(1/l) / (2D)) (sqrt for l = 2), or a given t.
+R17 Gap probing (plain Falconn): a pair's probe score is fl32(s - s_top) with s its pair score
+    and s_top = fl32(a_0 + b_0) its table's best (l = 1: fl32(a_i - a_0)), so the cost of a bucket
+    is the loss of projection summed over the functions; ranked as R7.
 
 Parity pinned: every function below is pinned by a test against a closed form,
 an invariant stated by the paper, a special case, or brute-force enumeration.
@@ -347,12 +350,14 @@ def query_lists(index: Index, q: np.ndarray):
             for t in range(index.L)]
 
 
-def probes(index: Index, q: np.ndarray, qProbes: int) -> np.ndarray:
+def probes(index: Index, q: np.ndarray, qProbes: int, score: str = "sum") -> np.ndarray:
     """The global top-qProbes (table, bucket) of one query, best first (reading R7).
 
     Every (table, pair) is scored by the float32 sum of its |projections|
     (l = 1: the single |projection|) and ranked by
     (score desc, table asc, position1 asc, position2 asc).
+    score "gap": the multi-probe score of plain Falconn (Section 2.2): the float32 difference
+    between the pair's score and the best pair of its table (reading R17), ranked the same way.
     Returns int64 [min(qProbes, L*D^l)] of table * (2D)^l + bucket.
     """
     D, l, L = index.D, index.l, index.L
@@ -366,6 +371,9 @@ def probes(index: Index, q: np.ndarray, qProbes: int) -> np.ndarray:
                       for t in range(L)])                                          # [L][D][D]
         b = np.stack([lists[t][0].code[0][:, None].astype(np.int64) * (2 * D)
                       + lists[t][1].code[0][None, :] for t in range(L)])
+    if score == "gap":
+        top = s.reshape(L, -1)[:, 0].copy()                       # position (0, 0): each table's best
+        s = (s - top.reshape((L,) + (1,) * l)).astype(np.float32)
     s = s.reshape(-1)
     b = (b + (np.arange(L, dtype=np.int64) * NB).reshape((L,) + (1,) * l)).reshape(-1)
     # flat order of s is (table, pos1, pos2) lexicographic, so a stable sort on -s gives R7
@@ -402,7 +410,7 @@ def topk_order(scores: np.ndarray, ids: np.ndarray, k: int):
     return out_i, out_s
 
 
-def query(index: Index, Q: np.ndarray, k: int, qProbes: int):
+def query(index: Index, Q: np.ndarray, k: int, qProbes: int, score: str = "sum"):
     """Top-k ids and float64 scores of every query, with the probe / candidate counts."""
     Q = np.atleast_2d(np.asarray(Q, dtype=np.float32))
     m = Q.shape[0]
@@ -411,7 +419,7 @@ def query(index: Index, Q: np.ndarray, k: int, qProbes: int):
     stats = np.zeros((m, 3), dtype=np.int64)    # probes, probed entries (with repeats), unique
     NB = n_buckets(index.D, index.l)
     for i in range(m):
-        pl = probes(index, Q[i], qProbes)
+        pl = probes(index, Q[i], qProbes, score)
         cand = candidates(index, pl)
         ent = 0
         for p in pl:

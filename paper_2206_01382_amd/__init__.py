@@ -5,7 +5,8 @@ The functions below are the C entry points with Python argument marshalling; see
 """
 from ._lib import (  # noqa: F401
     FPP_EINVAL, FPP_ECAPACITY, FPP_EHIP, FPP_ENOMEM, FPP_ESTATE, FPP_OK, FPP_STORE_BF16, FPP_STORE_FP32,
-    FPP_STORE_FP8, FPP_FILTER_FRACTION, FPP_FILTER_THRESHOLD, FppError, LIB_PATH, fpp_build_index,
+    FPP_STORE_FP8, FPP_FILTER_FRACTION, FPP_FILTER_THRESHOLD, FPP_PROBE_GAP, FPP_PROBE_SUM, FppError,
+    LIB_PATH, fpp_build_index,
     fpp_debug_build_records, fpp_debug_center, fpp_debug_export_store, fpp_normal_quantile,
     fpp_debug_export_table, fpp_debug_probes, fpp_debug_query_lists, fpp_debug_signs, fpp_free_index,
     fpp_index_get_info, fpp_index_table_sizes, fpp_last_error, fpp_query, fpp_query_batch,

@@ -39,8 +39,14 @@ class fpp_build_opts(ctypes.Structure):
                 ("kappa", c_i32), ("center", c_i32), ("filter", c_i32), ("threshold", c_f32)]
 
 
+FPP_PROBE_SUM = 0
+FPP_PROBE_GAP = 1
+PROBE_SCORES = {"sum": FPP_PROBE_SUM, "gap": FPP_PROBE_GAP}
+
+
 class fpp_query_opts(ctypes.Structure):
-    _fields_ = [("store", c_i32), ("rerank_R", c_i32), ("stats", c_vp), ("stage_ms", c_vp)]
+    _fields_ = [("store", c_i32), ("rerank_R", c_i32), ("stats", c_vp), ("stage_ms", c_vp),
+                ("probe_score", c_i32)]
 
 
 class fpp_index_info(ctypes.Structure):
@@ -53,7 +59,7 @@ class fpp_index_info(ctypes.Structure):
 
 class fpp_server_opts(ctypes.Structure):
     _fields_ = [("scratch_bytes", c_i64), ("n_streams", c_i32), ("max_batch", c_i32),
-                ("store", c_i32), ("rerank_R", c_i32)]
+                ("store", c_i32), ("rerank_R", c_i32), ("probe_score", c_i32)]
 
 
 class fpp_server_stats(ctypes.Structure):
@@ -89,7 +95,7 @@ SIGNATURES = {
     "fpp_debug_query_lists": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
     "fpp_debug_build_records": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "fpp_debug_export_table": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
-    "fpp_debug_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp]),
+    "fpp_debug_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp]),
     "fpp_debug_export_store": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "fpp_debug_center": (c_i32, [c_vp, c_vp]),
     "fpp_normal_quantile": (ctypes.c_double, [ctypes.c_double]),
@@ -168,7 +174,7 @@ def fpp_free_index(h):
 
 
 def fpp_query(h, Q, k: int, qProbes: int, *, store: str = "fp32", rerank_R: int = 0, stats: bool = False,
-              stream=None, out=None, stage_ms=None):
+              stream=None, out=None, stage_ms=None, probe_score: str = "sum"):
     """Top-k of every row of Q (GPU float32 [m][d]) -> (ids int32 [m][k], scores float32 [m][k][, stats]).
 
     ``stage_ms``: optional numpy float64 array of 4 that receives per-stage milliseconds
@@ -186,7 +192,8 @@ def fpp_query(h, Q, k: int, qProbes: int, *, store: str = "fp32", rerank_R: int 
     if stage_ms is not None and (stage_ms.dtype != np.float64 or stage_ms.shape != (4,)):
         raise ValueError("stage_ms must be a float64 array of 4")
     o = fpp_query_opts(STORES[store], rerank_R, c_vp(st.data_ptr()) if stats and m else None,
-                       stage_ms.ctypes.data_as(c_vp) if stage_ms is not None else None)
+                       stage_ms.ctypes.data_as(c_vp) if stage_ms is not None else None,
+                       PROBE_SCORES[probe_score])
     _check(lib().fpp_query_ex(h, qp, m, k, qProbes, ctypes.byref(o),
                               c_vp(ids.data_ptr()) if m else c_vp(0), c_vp(sc.data_ptr()) if m else c_vp(0),
                               _stream(stream)))
@@ -194,7 +201,7 @@ def fpp_query(h, Q, k: int, qProbes: int, *, store: str = "fp32", rerank_R: int 
 
 
 def fpp_query_batch(h, Q, k, qProbes, *, store: str = "fp32", rerank_R: int = 0, stats: bool = False,
-                    stream=None):
+                    stream=None, probe_score: str = "sum"):
     """Mixed batch: per-query k and qProbes (sequences); results packed in query order."""
     torch = _torch()
     m = Q.shape[0]
@@ -206,7 +213,8 @@ def fpp_query_batch(h, Q, k, qProbes, *, store: str = "fp32", rerank_R: int = 0,
     ids = torch.empty(tot, dtype=torch.int32, device=Q.device)
     sc = torch.empty(tot, dtype=torch.float32, device=Q.device)
     st = torch.empty((m, 3), dtype=torch.int64, device=Q.device) if stats else None
-    o = fpp_query_opts(STORES[store], rerank_R, c_vp(st.data_ptr()) if stats and m else None, None)
+    o = fpp_query_opts(STORES[store], rerank_R, c_vp(st.data_ptr()) if stats and m else None, None,
+                       PROBE_SCORES[probe_score])
     _check(lib().fpp_query_batch(h, _dev(Q, torch.float32, "Q") if m else c_vp(0), m,
                                  ka.ctypes.data_as(c_vp), pa.ctypes.data_as(c_vp), ctypes.byref(o),
                                  c_vp(ids.data_ptr()) if tot else c_vp(0),
@@ -215,7 +223,7 @@ def fpp_query_batch(h, Q, k, qProbes, *, store: str = "fp32", rerank_R: int = 0,
 
 
 def fpp_query_workspace_bytes(h, m: int, k_max: int, qprobes_max: int, store: str = "fp32", rerank_R: int = 0):
-    o = fpp_query_opts(STORES[store], rerank_R, None, None)
+    o = fpp_query_opts(STORES[store], rerank_R, None, None, FPP_PROBE_SUM)
     return int(lib().fpp_query_workspace_bytes(h, m, k_max, qprobes_max, ctypes.byref(o)))
 
 
@@ -289,14 +297,14 @@ def fpp_debug_export_table(h, t: int):
     return off.astype(np.int64), ids[: int(sizes[t])]
 
 
-def fpp_debug_probes(h, Q, qProbes: int, stream=None):
+def fpp_debug_probes(h, Q, qProbes: int, stream=None, probe_score: str = "sum"):
     torch = _torch()
     inf = fpp_index_get_info(h)
     pairs = inf["L"] * (inf["D"] if inf["l"] == 1 else inf["D"] ** 2)
     qc = min(qProbes, pairs)
     out = torch.empty((Q.shape[0], qc), dtype=torch.int64, device=Q.device)
     _check(lib().fpp_debug_probes(h, _dev(Q, torch.float32, "Q"), Q.shape[0], qProbes,
-                                  c_vp(out.data_ptr()), _stream(stream)))
+                                  PROBE_SCORES[probe_score], c_vp(out.data_ptr()), _stream(stream)))
     return out
 
 
@@ -319,8 +327,9 @@ def fpp_debug_export_store(h, store: str, stream=None):
 # ------------------------------------------------------------------------------------------------
 # serving
 def fpp_server_create(h, *, scratch_bytes: int = 2 << 30, n_streams: int = 2, max_batch: int = 1024,
-                      store: str = "fp32", rerank_R: int = 0) -> c_vp:
-    o = fpp_server_opts(scratch_bytes, n_streams, max_batch, STORES[store], rerank_R)
+                      store: str = "fp32", rerank_R: int = 0, probe_score: str = "sum") -> c_vp:
+    o = fpp_server_opts(scratch_bytes, n_streams, max_batch, STORES[store], rerank_R,
+                        PROBE_SCORES[probe_score])
     sv = c_vp()
     _check(lib().fpp_server_create(h, ctypes.byref(o), ctypes.byref(sv)))
     return sv

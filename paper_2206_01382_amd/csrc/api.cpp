@@ -420,7 +420,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     FPP_HIP(launch_hash_query(ix, Qc, mc, d, la, lc, s));
     FPP_TRY(mark());
     FPP_HIP(launch_probe_select(ix, la, lc, mc, qs.qp_dev ? qs.qp_dev + c0 : nullptr, qs.qp_uniform,
-                                ly.qcap, probes, np, s));
+                                ly.qcap, qs.probe_score, probes, np, s));
     FPP_TRY(mark());
     ScoreArgs a{};
     a.Q = Qc;
@@ -468,6 +468,8 @@ static int query_common(const fpp_index* ix, QuerySpec& qs, hipStream_t s) {
   if (!qs.Q || !qs.ids_out || !qs.scores_out) return set_error("Q, ids_out and scores_out must be non-NULL"), FPP_EINVAL;
   FPP_TRY(check_store(ix, qs.store));
   if (qs.R_opt < -1 || qs.R_opt > kMaxK) return set_error("rerank_R=%d out of [-1, %d]", qs.R_opt, kMaxK), FPP_EINVAL;
+  if (qs.probe_score != FPP_PROBE_SUM && qs.probe_score != FPP_PROBE_GAP)
+    return set_error("unknown probe_score %d", qs.probe_score), FPP_EINVAL;
 
   DeviceScratch host_arrays_unused;
   unsigned char* arrays = nullptr;
@@ -576,6 +578,7 @@ void fpp_default_query_opts(fpp_query_opts* o) {
   o->rerank_R = 0;
   o->stats = nullptr;
   o->stage_ms = nullptr;
+  o->probe_score = FPP_PROBE_SUM;
 }
 
 int fpp_build_index(const float* X, int64_t n, int32_t d, int32_t L, int32_t D, float alpha,
@@ -617,6 +620,7 @@ int fpp_query_ex(const fpp_index* index, const float* Q, int64_t m, int32_t k, i
   if (opts) {
     qs.store = opts->store;
     qs.R_opt = opts->rerank_R;
+    qs.probe_score = opts->probe_score;
     qs.stats = opts->stats;
     qs.stage_ms = opts->stage_ms;
   }
@@ -637,6 +641,7 @@ int fpp_query_batch(const fpp_index* index, const float* Q, int64_t m, const int
   if (opts) {
     qs.store = opts->store;
     qs.R_opt = opts->rerank_R;
+    qs.probe_score = opts->probe_score;
     qs.stats = opts->stats;
     qs.stage_ms = opts->stage_ms;
   }
@@ -756,9 +761,11 @@ int fpp_debug_export_table(const fpp_index* ix, int32_t t, uint32_t* offsets_out
 }
 
 int fpp_debug_probes(const fpp_index* ix, const float* Q, int64_t m, int32_t qProbes,
-                     int64_t* probes_out, void* stream) {
+                     int32_t probe_score, int64_t* probes_out, void* stream) {
   if (!ix || (m > 0 && (!Q || !probes_out))) return set_error("NULL argument"), FPP_EINVAL;
   if (qProbes < 1) return set_error("qProbes < 1"), FPP_EINVAL;
+  if (probe_score != FPP_PROBE_SUM && probe_score != FPP_PROBE_GAP)
+    return set_error("unknown probe_score %d", probe_score), FPP_EINVAL;
   if (m <= 0) return FPP_OK;
   hipStream_t s = (hipStream_t)stream;
   const int32_t qcap = (int32_t)std::min<int64_t>(qProbes, total_pairs(ix));
@@ -773,7 +780,7 @@ int fpp_debug_probes(const fpp_index* ix, const float* Q, int64_t m, int32_t qPr
   FPP_TRY(sc.get(&pr, (size_t)m * qcap));
   FPP_TRY(sc.get(&np, (size_t)m));
   FPP_HIP(launch_hash_query(ix, Q, m, ix->d, la, lc, s));
-  FPP_HIP(launch_probe_select(ix, la, lc, m, nullptr, qProbes, qcap, pr, np, s));
+  FPP_HIP(launch_probe_select(ix, la, lc, m, nullptr, qProbes, qcap, probe_score, pr, np, s));
   std::vector<uint32_t> h((size_t)m * qcap);
   std::vector<int32_t> hn((size_t)m);
   FPP_HIP(hipMemcpyAsync(h.data(), pr, h.size() * 4, hipMemcpyDeviceToHost, s));

@@ -126,7 +126,7 @@ double normal_quantile(double p);
 // nprobe[m] receives the count per query.
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc,
                                int64_t m, const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
-                               uint32_t* probes, int32_t* nprobe, hipStream_t s);
+                               int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s);
 
 // Candidate gather, dedup, scoring and top-k (plus the FP32 rerank of a short list).
 struct ScoreArgs {
@@ -173,6 +173,7 @@ struct QuerySpec {
   int32_t k_max = 0, qp_max = 0;
   int32_t store = FPP_STORE_FP32;
   int32_t R_opt = 0;                   // rerank short-list length (0 = max(100, 2k))
+  int32_t probe_score = FPP_PROBE_SUM;  // FPP_PROBE_*
   int32_t* ids_out = nullptr;
   float* scores_out = nullptr;
   int64_t* stats = nullptr;

@@ -37,25 +37,46 @@ struct Lists {
   }
 };
 
+// Order-preserving map of floats to u32 (and back): the bisection runs on these keys so that the
+// (non-positive) gap scores search like the (non-negative) sums.
+__device__ __forceinline__ uint32_t ord_of(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float of_ord(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// Probe score of a pair: the float32 sum of its |projections|, minus `off` (0 for Falconn++;
+// the table's best pair for the gap score of plain Falconn). x - 0 == x, so both modes share
+// every walk below.
+__device__ __forceinline__ float pair_score(float a, float b, float off) { return (a + b) - off; }
+
+// Offset of table t: 0, or its best pair under the gap score.
+__device__ __forceinline__ float table_offset(const Lists& ls, int t, int l, bool gap) {
+  if (!gap) return 0.0f;
+  return l == 1 ? ls.get(t, 0) : ls.get(2 * t, 0) + ls.get(2 * t + 1, 0);
+}
+
 // min(cap, #pairs of table t with score >= tau); A = list 2t (or t for l = 1), B = list 2t + 1.
 // The walk stops once `cap` pairs are counted, so its depth is bounded by cap.
 __device__ __forceinline__ uint64_t count_table(const Lists& ls, int t, int l, float tau,
-                                                uint64_t cap) {
+                                                uint64_t cap, float off) {
   const int D = ls.D;
   const int lim = cap < (uint64_t)D ? (int)cap : D;
   if (l == 1) {
     int c = 0;
-    while (c < lim && ls.get(t, c) >= tau) ++c;
+    while (c < lim && ls.get(t, c) - off >= tau) ++c;
     return (uint64_t)c;
   }
   const int la = 2 * t, lb = 2 * t + 1;
   const float a0 = ls.get(la, 0);
   int j = 0;
-  while (j < lim && a0 + ls.get(lb, j) >= tau) ++j;
+  while (j < lim && pair_score(a0, ls.get(lb, j), off) >= tau) ++j;
   uint64_t c = 0;
   for (int i = 0; i < D && j > 0; ++i) {
     const float ai = ls.get(la, i);
-    while (j > 0 && !(ai + ls.get(lb, j - 1) >= tau)) --j;
+    while (j > 0 && !(pair_score(ai, ls.get(lb, j - 1), off) >= tau)) --j;
     c += (uint64_t)j;
     if (c >= cap) return cap;
   }
@@ -114,7 +135,7 @@ __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t& total, 
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     const float* __restrict__ la, const uint16_t* __restrict__ lc, int64_t m, int L, int l, int D,
     int M, int64_t NB, const int32_t* __restrict__ qp_arr, int32_t qp_uniform, int32_t qcap,
-    uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
+    int gap_score, uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* red = reinterpret_cast<uint64_t*>(smem);        // kProbeWaves words
   float* pre = reinterpret_cast<float*>(smem + 64);         // [l][L][M + 1] list prefixes
@@ -175,19 +196,22 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   // c = ceil(qP / L), every table has at least c pairs scoring >= its bound (row 0 for c <= D,
   // else the first ceil(c / D) full rows), so the minimum bound over tables counts >= L c >= qP.
   const uint64_t cpt = (qP + L - 1) / L;
-  float mx = 0.0f, mn = INFINITY;
+  const bool gap = gap_score != 0;
+  float mx = -INFINITY, mn = INFINITY;
   for (int t = tid; t < L; t += kProbeThreads) {
     float top, bound;
+    const float off = table_offset(ls, t, l, gap);
     if (l == 1) {
-      top = ls.get(t, 0);
-      bound = cpt <= (uint64_t)D ? ls.get(t, (int)cpt - 1) : 0.0f;
+      top = ls.get(t, 0) - off;
+      bound = cpt <= (uint64_t)D ? ls.get(t, (int)cpt - 1) - off : -INFINITY;
     } else {
-      top = ls.get(2 * t, 0) + ls.get(2 * t + 1, 0);
+      top = pair_score(ls.get(2 * t, 0), ls.get(2 * t + 1, 0), off);
       if (cpt <= (uint64_t)D) {
-        bound = ls.get(2 * t, 0) + ls.get(2 * t + 1, (int)cpt - 1);
+        bound = pair_score(ls.get(2 * t, 0), ls.get(2 * t + 1, (int)cpt - 1), off);
       } else {
         const uint64_t rows = (cpt + D - 1) / D;
-        bound = rows <= (uint64_t)D ? ls.get(2 * t, (int)rows - 1) + ls.get(2 * t + 1, D - 1) : 0.0f;
+        bound = rows <= (uint64_t)D ? pair_score(ls.get(2 * t, (int)rows - 1), ls.get(2 * t + 1, D - 1), off)
+                                    : -INFINITY;
       }
     }
     mx = fmaxf(mx, top);
@@ -215,14 +239,14 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   // Counts are capped at qP + 1 per table: a capped sum is >= qP exactly when the true sum is,
   // and equals qP only when no table was capped, so every decision below is the uncapped one.
   const uint64_t cap = qP + 1;
-  uint32_t lo = __float_as_uint(mn), hi = __float_as_uint(mx) + 1u;   // cnt(lo) >= qP > cnt(hi)
+  uint32_t lo = ord_of(mn), hi = ord_of(mx) + 1u;   // cnt(lo) >= qP > cnt(hi), in key order
   uint64_t c_hi = 0;
   bool exact = false;
   while (hi - lo > 1u) {
     const uint32_t mid = lo + (hi - lo) / 2u;
-    const float tau = __uint_as_float(mid);
+    const float tau = of_ord(mid);
     uint64_t c = 0;
-    for (int t = tid; t < L; t += kProbeThreads) c += count_table(ls, t, l, tau, cap);
+    for (int t = tid; t < L; t += kProbeThreads) c += count_table(ls, t, l, tau, cap, table_offset(ls, t, l, gap));
     c = block_sum_u64(c, red);
     if (c == qP) {
       lo = mid;
@@ -236,8 +260,8 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
       c_hi = c;
     }
   }
-  const float thr_gt = __uint_as_float(exact ? lo : hi);
-  const float tau_eq = __uint_as_float(lo);
+  const float thr_gt = of_ord(exact ? lo : hi);
+  const float tau_eq = of_ord(lo);
   const uint64_t c_gt = exact ? qP : c_hi;
   const uint64_t need = qP - c_gt;
   uint32_t* out = probes + (size_t)q * qcap;
@@ -248,10 +272,11 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   for (int tb = 0; tb < L; tb += kProbeThreads) {
     const int t = tb + tid;
     uint64_t n_gt = 0, n_eq = 0;
+    const float off = t < L ? table_offset(ls, t, l, gap) : 0.0f;
     if (t < L) {
       // every table holds at most c_gt <= qP pairs above thr_gt; ties are only needed up to `need`
-      n_gt = count_table(ls, t, l, thr_gt, cap);
-      if (need) n_eq = count_table(ls, t, l, tau_eq, n_gt + need) - n_gt;
+      n_gt = count_table(ls, t, l, thr_gt, cap, off);
+      if (need) n_eq = count_table(ls, t, l, tau_eq, n_gt + need, off) - n_gt;
     }
     uint64_t tot_gt, tot_eq;
     const uint64_t pos_gt0 = run_gt + block_scan_u64(n_gt, tot_gt, red);
@@ -272,16 +297,16 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     const int la_ = 2 * t, lb_ = 2 * t + 1;
     int jg = 0, je = 0;
     const float a0 = ls.get(la_, 0);
-    while (jg < D && a0 + ls.get(lb_, jg) >= thr_gt) ++jg;
+    while (jg < D && pair_score(a0, ls.get(lb_, jg), off) >= thr_gt) ++jg;
     if (need) {
       je = jg;
-      while (je < D && a0 + ls.get(lb_, je) >= tau_eq) ++je;
+      while (je < D && pair_score(a0, ls.get(lb_, je), off) >= tau_eq) ++je;
     }
     for (int i = 0; i < D && (jg > 0 || je > 0); ++i) {
       const float ai = ls.get(la_, i);
-      while (jg > 0 && !(ai + ls.get(lb_, jg - 1) >= thr_gt)) --jg;
+      while (jg > 0 && !(pair_score(ai, ls.get(lb_, jg - 1), off) >= thr_gt)) --jg;
       if (need)
-        while (je > 0 && !(ai + ls.get(lb_, je - 1) >= tau_eq)) --je;
+        while (je > 0 && !(pair_score(ai, ls.get(lb_, je - 1), off) >= tau_eq)) --je;
       const uint32_t rowb = tbase + (uint32_t)C1[i] * twoD;
       for (int j = 0; j < jg; ++j) out[pg++] = rowb + C2[j];
       for (int j = jg; j < je && te < need; ++j, ++te) out[c_gt + te] = rowb + C2[j];
@@ -308,7 +333,7 @@ int probe_prefix(const fpp_index* ix, int32_t qcap) {
 
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc, int64_t m,
                                const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
-                               uint32_t* probes, int32_t* nprobe, hipStream_t s) {
+                               int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const int M = probe_prefix(ix, qcap);
   const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + ix->L + 1) * 4;
@@ -318,7 +343,7 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(probe_kernel, dim3((unsigned)m), dim3(kProbeThreads), lds, s, la, lc, m, ix->L,
-                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probes, nprobe);
+                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probe_score, probes, nprobe);
   return hipGetLastError();
 }
 

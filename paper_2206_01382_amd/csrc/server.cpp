@@ -221,6 +221,7 @@ int launch_batch(fpp_server* sv, Slot& s) {
   qs.qp_max = qpmax;
   qs.store = sv->opts.store;
   qs.R_opt = sv->opts.rerank_R;
+  qs.probe_score = sv->opts.probe_score;
   qs.ids_out = s.d_ids;
   qs.scores_out = s.d_sc;
   const Layout ly = plan_layout(ix, m, qpmax, kmax, qs.store, qs.R_opt, INT64_MAX, false);
@@ -337,6 +338,7 @@ void fpp_default_server_opts(fpp_server_opts* o) {
   o->max_batch = 1024;
   o->store = FPP_STORE_FP32;
   o->rerank_R = 0;
+  o->probe_score = FPP_PROBE_SUM;
 }
 
 int fpp_server_create(const fpp_index* ix, const fpp_server_opts* opts, fpp_server** out) {
@@ -348,6 +350,8 @@ int fpp_server_create(const fpp_index* ix, const fpp_server_opts* opts, fpp_serv
   if (o.max_batch < 1) return set_error("max_batch=%d < 1", o.max_batch), FPP_EINVAL;
   if (o.scratch_bytes < 1) return set_error("scratch_bytes < 1"), FPP_EINVAL;
   if (o.rerank_R < -1 || o.rerank_R > kMaxK) return set_error("rerank_R out of range"), FPP_EINVAL;
+  if (o.probe_score != FPP_PROBE_SUM && o.probe_score != FPP_PROBE_GAP)
+    return set_error("unknown probe_score %d", o.probe_score), FPP_EINVAL;
   FPP_TRY(check_store(ix, o.store));
   std::unique_ptr<fpp_server> sv(new fpp_server());
   sv->ix = ix;

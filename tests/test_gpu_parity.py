@@ -239,6 +239,22 @@ def test_probe_sets_bit_exact(name):
             assert sorted(g[r].tolist()) == sorted(ref.tolist()), (qp, r)
 
 
+@pytest.mark.parametrize("name", ["c1_gauss_10k_d64", "l2_clustered", "p512_d300_D256", "l1_D8_iprobes3"])
+def test_gap_probe_sets_bit_exact(name):
+    """Plain Falconn's gap score: probe sets bit-exact, and queries match the oracle."""
+    w, oi, h, Xd, Qd = built(name)
+    total = w["L"] * (w["D"] ** w["l"])
+    for qp in sorted({1, 3, w["L"], 4 * w["L"], 50 * w["L"], total}):
+        g = F().fpp_debug_probes(h, Qd, qp, probe_score="gap").cpu().numpy()
+        for r in range(w["Q"].shape[0]):
+            ref = O.probes(oi, w["Q"][r], qp, "gap")
+            assert sorted(g[r].tolist()) == sorted(ref.tolist()), (qp, r)
+    qp = 4 * w["L"]
+    ids, sc = F().fpp_query(h, Qd, 10, qp, probe_score="gap")
+    oids, osc, _ = O.query(oi, w["Q"], 10, qp, "gap")
+    assert check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, w["X"].shape[1]) <= 3
+
+
 @pytest.mark.parametrize("name", list(CONFIGS))
 @pytest.mark.parametrize("k", [1, 10, 100])
 def test_query_fp32_matches_oracle(name, k):

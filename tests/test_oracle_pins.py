@@ -343,7 +343,7 @@ def test_threshold_zero_keeps_every_record():
 
 
 # ------------------------------------------------------------------ query
-def _brute_probes(idx, q, qProbes):
+def _brute_probes(idx, q, qProbes, gap=False):
     D, L = idx.D, idx.L
     cands = []
     for t in range(L):
@@ -352,9 +352,14 @@ def _brute_probes(idx, q, qProbes):
         for f in range(2):
             order = sorted(range(D), key=lambda i: (-abs(float(y[f][i])), i))
             ranks.append({i: r for r, i in enumerate(order)})
+        best = max(np.float32(np.float32(abs(y[0][i])) + np.float32(abs(y[1][j])))
+                   for i in range(D) for j in range(D))
         for i in range(D):
             for j in range(D):
-                s = float(np.float32(np.float32(abs(y[0][i])) + np.float32(abs(y[1][j]))))
+                s = np.float32(np.float32(abs(y[0][i])) + np.float32(abs(y[1][j])))
+                if gap:      # plain Falconn: the loss against the table's best pair
+                    s = np.float32(s - best)
+                s = float(s)
                 c1 = i if y[0][i] >= 0 else i + D
                 c2 = j if y[1][j] >= 0 else j + D
                 cands.append((-s, t, ranks[0][i], ranks[1][j], t * 4 * D * D + c1 * 2 * D + c2))
@@ -368,6 +373,27 @@ def test_probe_ranking_equals_enumeration(qProbes):
     idx = O.build_index(X, L=3, D=4, alpha=0.5, iProbes=2, seed=5, l=2)
     q = _uniform_data(1, 12, 8)[0]
     assert O.probes(idx, q, qProbes).tolist() == _brute_probes(idx, q, qProbes)
+
+
+@pytest.mark.parametrize("qProbes", [1, 3, 5, 37, 10_000])
+def test_gap_probe_ranking_equals_enumeration(qProbes):
+    X = _uniform_data(50, 12, 7)
+    idx = O.build_index(X, L=3, D=4, alpha=0.5, iProbes=2, seed=5, l=2)
+    q = _uniform_data(1, 12, 9)[0]
+    assert O.probes(idx, q, qProbes, "gap").tolist() == _brute_probes(idx, q, qProbes, gap=True)
+
+
+def test_gap_probing_takes_each_tables_best_bucket_first():
+    """With qProbes <= L the gap score (0 for every table's best pair) selects the home bucket of
+    the first qProbes tables, as plain Falconn does before any second probe."""
+    X = _uniform_data(200, 16, 10)
+    idx = O.build_index(X, L=6, D=8, alpha=1.0, iProbes=1, seed=11, l=2)
+    q = _uniform_data(1, 16, 12)[0]
+    home = O.hash_codes(q[None, :], idx.signs, 8)[0]
+    NB = O.n_buckets(8, 2)
+    for qp in (1, 4, 6):
+        got = O.probes(idx, q, qp, "gap").tolist()
+        assert got == [t * NB + int(home[t, 0]) * 16 + int(home[t, 1]) for t in range(qp)]
 
 
 def test_full_probing_reaches_every_sign_consistent_point():
