@@ -45,6 +45,9 @@ extern "C" {
 #define FPP_STORE_FP32 0
 #define FPP_STORE_BF16 1   /* x rounded to bfloat16, nearest-even                                */
 #define FPP_STORE_FP8 2    /* per-vector scale s = max|x|/448; codes = OCP E4M3(x/s), nearest-even */
+#define FPP_STORE_SIMHASH 3 /* SimHash signatures (Section 4, "Falconn++ parameter settings"): the
+                               signs of the first D projections of the first F hash functions,
+                               F*D bits; approximate score = F*D - 2 * Hamming distance          */
 
 typedef struct fpp_index fpp_index;
 
@@ -53,7 +56,7 @@ typedef struct fpp_build_opts {
   int32_t l;              /* cross-polytope functions concatenated per table: 1 or 2 (2). Section 4
                              uses 2, giving (2D)^2 buckets per table.                            */
   int32_t stores;         /* bit mask of extra low-precision stores to build: 1<<FPP_STORE_BF16,
-                             1<<FPP_STORE_FP8 (0 = FP32 only)                                    */
+                             1<<FPP_STORE_FP8, 1<<FPP_STORE_SIMHASH (0 = FP32 only)              */
   int32_t keep_rounding;  /* 0: a bucket of B records keeps ceil(alpha*B/iProbes) (default);
                              1: floor(...). alpha is taken to 6 decimals.                       */
   int32_t tables_per_pass;/* tables hashed and sorted per pass (0 = chosen from free memory)    */
@@ -70,6 +73,10 @@ typedef struct fpp_build_opts {
   float threshold;        /* t for FPP_FILTER_THRESHOLD; <= 0: t = Phi^-1(1 - alpha^(1/l) / (2D)),
                              so that a point reaches a given bucket with probability alpha/(2D)^l
                              for Gaussian projections (Phi^-1 by Wichura's algorithm AS 241)    */
+  int32_t simhash_functions; /* F for FPP_STORE_SIMHASH: hash functions (t * l + f order) whose
+                             projection signs form a signature; a multiple of l with
+                             F * D <= 1024; 0 = the largest multiple of l with F * D <= 256
+                             (at least l)                                                       */
 } fpp_build_opts;
 
 #define FPP_FILTER_FRACTION 0
@@ -110,7 +117,8 @@ void fpp_free_index(fpp_index* index);
 /* Query options (fpp_default_query_opts fills the defaults shown). */
 typedef struct fpp_query_opts {
   int32_t store;       /* store scored during the candidate pass: FPP_STORE_FP32 (exact scores, 0),
-                          FPP_STORE_BF16 or FPP_STORE_FP8 (approximate; requires that store)     */
+                          FPP_STORE_BF16, FPP_STORE_FP8 or FPP_STORE_SIMHASH (approximate;
+                          requires that store)                                                  */
   int32_t rerank_R;    /* low-precision stores: short-list length re-scored exactly in FP32
                           (0 = max(100, 2k)); k <= R <= 512. -1: no rerank, the top-k of the
                           low-precision pass is returned with its approximate scores           */
@@ -176,6 +184,7 @@ typedef struct fpp_index_info {
   int32_t filter;          /* FPP_FILTER_*                                           */
   float threshold;         /* FPP_FILTER_THRESHOLD: the float32 bound on |y| the build
                               compared against (fl32(P * t)); 0 otherwise             */
+  int32_t simhash_bits;    /* F * D of the SimHash store (0 if not built)           */
 } fpp_index_info;
 
 int fpp_index_get_info(const fpp_index* index, fpp_index_info* info);
@@ -271,7 +280,9 @@ int fpp_debug_probes(const fpp_index* index, const float* Q, int64_t m, int32_t 
 int fpp_debug_center(const fpp_index* index, float* c_out);
 
 /* A low-precision store: store FPP_STORE_BF16 -> device uint16 [n][d]; FPP_STORE_FP8 -> device
- * uint8 [n][d] codes plus device float32 [n] scales (scales_out ignored for BF16). */
+ * uint8 [n][d] codes plus device float32 [n] scales (scales_out ignored for BF16 and SimHash);
+ * FPP_STORE_SIMHASH -> device uint32 [n][ceil(F*D/32)] signature words (bit b of a signature is
+ * word b / 32, bit b % 32; b = g * D + i is set when projection i of function g is negative). */
 int fpp_debug_export_store(const fpp_index* index, int32_t store, void* codes_out,
                            float* scales_out, void* stream);
 

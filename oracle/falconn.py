@@ -44,6 +44,9 @@ R15 Centering: c_j = fl32(running float64 sum of x_ij over rows in order / n); t
     fl32(x - c); queries are hashed unchanged; scores are x^T q on the uncentred data.
 R16 Global threshold: keep a record when each |y| of its pair is >= fl32(P * t) with
     t = Phi^-1(1 - alpha^(1/l) / (2D)) (sqrt for l = 2), or a given t.
+R18 SimHash store: bit g*D + i of a signature is the sign (y_i < 0) of projection i of hash
+    function g = t*l + f, for the first F functions; approximate score = F*D - 2 * Hamming;
+    data signatures use the uncentred vectors (the queries' rotation).
 R17 Gap probing (plain Falconn): a pair's probe score is fl32(s - s_top) with s its pair score
     and s_top = fl32(a_0 + b_0) its table's best (l = 1: fl32(a_i - a_0)), so the cost of a bucket
     is the loss of projection summed over the functions; ranked as R7.
@@ -532,15 +535,48 @@ def dequantized_store(X: np.ndarray, storage: str):
     raise ValueError(storage)
 
 
+def simhash_bits(V: np.ndarray, signs: np.ndarray, D: int, F: int) -> np.ndarray:
+    """SimHash signature (Section 4: the signs of projections already computed for the tables):
+    bit g*D + i is 1 when projection i of hash function g (in table-major, function-minor order)
+    is negative (reading R18). Returns bool [n][F*D]."""
+    L, l = signs.shape[:2]
+    V = np.asarray(V, dtype=np.float32)
+    out = np.zeros((V.shape[0], F * D), dtype=bool)
+    for g in range(F):
+        t, f = divmod(g, l)
+        out[:, g * D:(g + 1) * D] = rotate(V, signs[t, f], D) < np.float32(0.0)
+    return out
+
+
+def simhash_words(bits: np.ndarray) -> np.ndarray:
+    """Pack signature bits little-endian into 32-bit words: bit b -> word b // 32, bit b % 32."""
+    n, nb = bits.shape
+    w = (nb + 31) // 32
+    padded = np.zeros((n, w * 32), dtype=np.uint64)
+    padded[:, :nb] = bits
+    weights = (np.uint64(1) << np.arange(32, dtype=np.uint64))
+    return (padded.reshape(n, w, 32) * weights).sum(axis=2).astype(np.uint32)
+
+
+def simhash_score(sig_x: np.ndarray, sig_q: np.ndarray) -> np.ndarray:
+    """Approximate score of SimHash: bits - 2 * Hamming distance (a float, exact)."""
+    ham = np.count_nonzero(sig_x != sig_q[None, :], axis=1)
+    return (sig_x.shape[1] - 2 * ham).astype(np.float64)
+
+
 def query_reranked(index: Index, Q: np.ndarray, k: int, qProbes: int, R: int, storage: str,
-                   store: np.ndarray | None = None):
+                   store: np.ndarray | None = None, simhash_functions: int = 0):
     """Low-precision form: approximate scores on the store, short list of R, exact float64 rerank.
 
     Short list = first R candidates by (approximate score desc, id asc); the final answer
     is the top-k of the short list by exact score (reading R8).
     """
     Q = np.atleast_2d(np.asarray(Q, dtype=np.float32))
-    if store is None:
+    if storage == "simhash":
+        F = simhash_functions
+        store = simhash_bits(index.X, index.signs, index.D, F) if store is None else store
+        qsig = simhash_bits(Q, index.signs, index.D, F)
+    elif store is None:
         store = dequantized_store(index.X, storage)
     m = Q.shape[0]
     ids = np.empty((m, k), dtype=np.int64)
@@ -549,7 +585,10 @@ def query_reranked(index: Index, Q: np.ndarray, k: int, qProbes: int, R: int, st
     for i in range(m):
         pl = probes(index, Q[i], qProbes)
         cand = candidates(index, pl)
-        approx = store[cand] @ Q[i].astype(np.float64)
+        if storage == "simhash":
+            approx = simhash_score(store[cand], qsig[i])
+        else:
+            approx = store[cand] @ Q[i].astype(np.float64)
         sl, _ = topk_order(approx, cand, R)
         short[i] = sl
         sl = sl[sl >= 0]

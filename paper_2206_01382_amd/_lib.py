@@ -24,7 +24,8 @@ FPP_ESTATE = -5
 FPP_STORE_FP32 = 0
 FPP_STORE_BF16 = 1
 FPP_STORE_FP8 = 2
-STORES = {"fp32": FPP_STORE_FP32, "bf16": FPP_STORE_BF16, "fp8": FPP_STORE_FP8}
+FPP_STORE_SIMHASH = 3
+STORES = {"fp32": FPP_STORE_FP32, "bf16": FPP_STORE_BF16, "fp8": FPP_STORE_FP8, "simhash": FPP_STORE_SIMHASH}
 
 c_i32, c_i64, c_u64, c_f32, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float, ctypes.c_void_p
 
@@ -36,7 +37,8 @@ FILTERS = {"fraction": FPP_FILTER_FRACTION, "threshold": FPP_FILTER_THRESHOLD}
 
 class fpp_build_opts(ctypes.Structure):
     _fields_ = [("l", c_i32), ("stores", c_i32), ("keep_rounding", c_i32), ("tables_per_pass", c_i32),
-                ("kappa", c_i32), ("center", c_i32), ("filter", c_i32), ("threshold", c_f32)]
+                ("kappa", c_i32), ("center", c_i32), ("filter", c_i32), ("threshold", c_f32),
+                ("simhash_functions", c_i32)]
 
 
 FPP_PROBE_SUM = 0
@@ -54,7 +56,7 @@ class fpp_index_info(ctypes.Structure):
                 ("iProbes", c_i32), ("stores", c_i32), ("alpha", c_f32), ("seed", c_u64),
                 ("buckets_per_table", c_i64), ("total_ids", c_i64), ("max_bucket", c_i64),
                 ("device_bytes", c_i64), ("build_ms", ctypes.c_double), ("kappa", c_i32),
-                ("centered", c_i32), ("filter", c_i32), ("threshold", c_f32)]
+                ("centered", c_i32), ("filter", c_i32), ("threshold", c_f32), ("simhash_bits", c_i32)]
 
 
 class fpp_server_opts(ctypes.Structure):
@@ -156,12 +158,12 @@ def _stream(stream):
 def fpp_build_index(X, L: int, D: int, alpha: float, iProbes: int, seed: int, *, l: int = 2,
                     stores=(), keep_rounding: int = 0, tables_per_pass: int = 0, kappa: int = 0,
                     center: bool = False, filter: str = "fraction", threshold: float = 0.0,
-                    stream=None) -> c_vp:
+                    simhash_functions: int = 0, stream=None) -> c_vp:
     """Build an index over X (GPU float32 [n][d]); returns the opaque handle."""
     torch = _torch()
     xp = _dev(X, torch.float32, "X")
     o = fpp_build_opts(l, sum(1 << STORES[s] for s in stores), keep_rounding, tables_per_pass,
-                       kappa, int(bool(center)), FILTERS[filter], threshold)
+                       kappa, int(bool(center)), FILTERS[filter], threshold, simhash_functions)
     h = c_vp()
     _check(lib().fpp_build_index_ex(xp, X.shape[0], X.shape[1], L, D, alpha, iProbes, seed & (2 ** 64 - 1),
                                     ctypes.byref(o), _stream(stream), ctypes.byref(h)))
@@ -314,6 +316,9 @@ def fpp_debug_export_store(h, store: str, stream=None):
     n, d = inf["n"], inf["d"]
     if store == "bf16":
         codes = torch.empty((n, d), dtype=torch.int16, device="cuda")
+        scales = None
+    elif store == "simhash":
+        codes = torch.empty((n, (inf["simhash_bits"] + 31) // 32), dtype=torch.int32, device="cuda")
         scales = None
     else:
         codes = torch.empty((n, d), dtype=torch.uint8, device="cuda")

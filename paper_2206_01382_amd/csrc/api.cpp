@@ -142,7 +142,7 @@ static int dalloc(T** p, size_t count, int64_t* acc) {
 static void free_index_memory(fpp_index* ix) {
   if (!ix) return;
   void* ptrs[] = {ix->X, ix->Xbf16, ix->Xfp8, ix->fp8_scale, ix->sign_mask, ix->offsets, ix->ids,
-                  ix->center_vec};
+                  ix->center_vec, ix->Xsig};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -204,8 +204,16 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   FPP_TRY(validate_build(X, n, d, L, D, alpha, iProbes, o.l));
   if (!out) return set_error("out is NULL"), FPP_EINVAL;
   if (o.keep_rounding != 0 && o.keep_rounding != 1) return set_error("keep_rounding must be 0 or 1"), FPP_EINVAL;
-  if (o.stores & ~((1 << FPP_STORE_BF16) | (1 << FPP_STORE_FP8)))
+  if (o.stores & ~((1 << FPP_STORE_BF16) | (1 << FPP_STORE_FP8) | (1 << FPP_STORE_SIMHASH)))
     return set_error("unknown store bits 0x%x", o.stores), FPP_EINVAL;
+  int32_t sigF = 0;
+  if (o.stores & (1 << FPP_STORE_SIMHASH)) {
+    sigF = o.simhash_functions;
+    if (sigF == 0) sigF = std::max(o.l, (256 / D) / o.l * o.l);
+    if (sigF < 1 || sigF % o.l != 0 || sigF > L * o.l || (int64_t)sigF * D > 1024)
+      return set_error("simhash_functions=%d: need a multiple of l, at most L*l, with F*D <= 1024", sigF),
+             FPP_EINVAL;
+  }
   if (o.kappa < 0) return set_error("kappa=%d < 0", o.kappa), FPP_EINVAL;
   if (o.center != 0 && o.center != 1) return set_error("center must be 0 or 1"), FPP_EINVAL;
   if (o.filter != FPP_FILTER_FRACTION && o.filter != FPP_FILTER_THRESHOLD)
@@ -328,7 +336,27 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
     FPP_TRY(dalloc(&ix->Xfp8, (size_t)n * ix->ld8, &bytes));
     FPP_TRY(dalloc(&ix->fp8_scale, (size_t)n, &bytes));
   }
-  if (o.stores) FPP_HIP(launch_quantize(ix.get(), s));
+  if (o.stores & ((1 << FPP_STORE_BF16) | (1 << FPP_STORE_FP8))) FPP_HIP(launch_quantize(ix.get(), s));
+  if (sigF) {
+    // signatures: the sorted lists of the first F functions of every point, packed to bits
+    ix->sigF = sigF;
+    ix->ldsig = (int32_t)(((int64_t)sigF * D + 127) / 128 * 4);
+    FPP_TRY(dalloc(&ix->Xsig, (size_t)n * ix->ldsig, &bytes));
+    fpp_index view = *ix;
+    view.L = sigF / o.l;        // the first F functions, in (table, function) order
+    const int64_t rows = std::max<int64_t>(1, ((int64_t)256 << 20) / ((int64_t)sigF * D * 6));
+    DeviceScratch sg;
+    float* la = nullptr;
+    uint16_t* lc = nullptr;
+    FPP_TRY(sg.get(&la, (size_t)std::min(rows, n) * sigF * D));
+    FPP_TRY(sg.get(&lc, (size_t)std::min(rows, n) * sigF * D));
+    for (int64_t r0 = 0; r0 < n; r0 += rows) {
+      const int64_t nr = std::min(rows, n - r0);
+      FPP_HIP(launch_hash_query(&view, ix->X + r0 * ix->ldx, nr, ix->ldx, la, lc, s));
+      FPP_HIP(launch_pack_signs(lc, nr, sigF, D, sigF, ix->ldsig, ix->Xsig + r0 * ix->ldsig, s));
+    }
+    FPP_HIP(hipStreamSynchronize(s));
+  }
   FPP_HIP(hipStreamSynchronize(s));
   ix->device_bytes = bytes;
   ix->Xh = nullptr;   // the centred copy is released with this call's scratch
@@ -365,7 +393,8 @@ Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max
   ly.qcap = (int32_t)std::min<int64_t>(std::max(qp_max, 1), total_pairs(ix));
   ly.short_ld = (store == FPP_STORE_FP32 || R_opt < 0) ? 0 : short_list_len(R_opt, k_max);
   const int64_t LF = (int64_t)ix->L * ix->l;
-  const int64_t per_q = LF * ix->D * 6 + (int64_t)ly.qcap * 4 + 4 + (int64_t)ly.short_ld * 4 + 64;
+  const int64_t sigw = store == FPP_STORE_SIMHASH ? ix->ldsig : 0;
+  const int64_t per_q = LF * ix->D * 6 + (int64_t)ly.qcap * 4 + 4 + (int64_t)ly.short_ld * 4 + sigw * 4 + 64;
   ly.mc = std::max<int64_t>(1, std::min<int64_t>(m, budget / per_q));
   ly.gbm = gbm_in_scratch;
   ly.grid = score_grid_blocks(ix);
@@ -380,6 +409,8 @@ Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max
   o = a256(o + (size_t)ly.mc * 4);
   ly.off_short = o;
   o = a256(o + (size_t)ly.mc * ly.short_ld * 4);
+  ly.off_qsig = o;
+  o = a256(o + (size_t)ly.mc * sigw * 4);
   ly.off_gbm = o;
   if (ly.gbm) o = a256(o + overflow_bitmap_bytes(ix));
   ly.total = o;
@@ -390,7 +421,8 @@ int check_store(const fpp_index* ix, int32_t store) {
   if (store == FPP_STORE_FP32) return FPP_OK;
   if (store == FPP_STORE_BF16 && ix->Xbf16) return FPP_OK;
   if (store == FPP_STORE_FP8 && ix->Xfp8) return FPP_OK;
-  if (store == FPP_STORE_BF16 || store == FPP_STORE_FP8)
+  if (store == FPP_STORE_SIMHASH && ix->Xsig) return FPP_OK;
+  if (store == FPP_STORE_BF16 || store == FPP_STORE_FP8 || store == FPP_STORE_SIMHASH)
     return set_error("store %d was not built for this index", store), FPP_ESTATE;
   return set_error("unknown store %d", store), FPP_EINVAL;
 }
@@ -425,6 +457,13 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     ScoreArgs a{};
     a.Q = Qc;
     a.ldq = d;
+    if (qs.store == FPP_STORE_SIMHASH) {
+      // the query's signature from its sorted lists; the gather scores against it
+      uint32_t* qsig = (uint32_t*)(ws + ly.off_qsig);
+      FPP_HIP(launch_pack_signs(lc, mc, ix->L * ix->l, ix->D, ix->sigF, ix->ldsig, qsig, s));
+      a.Q = reinterpret_cast<const float*>(qsig);
+      a.ldq = ix->ldsig;
+    }
     a.m = mc;
     a.probes = probes;
     a.nprobe = np;
@@ -570,6 +609,7 @@ void fpp_default_build_opts(fpp_build_opts* o) {
   o->center = 0;
   o->filter = FPP_FILTER_FRACTION;
   o->threshold = 0.f;
+  o->simhash_functions = 0;
 }
 
 void fpp_default_query_opts(fpp_query_opts* o) {
@@ -678,6 +718,7 @@ int fpp_index_get_info(const fpp_index* ix, fpp_index_info* info) {
   info->centered = ix->centered;
   info->filter = ix->filter;
   info->threshold = ix->filter == FPP_FILTER_THRESHOLD ? ix->thr : 0.f;
+  info->simhash_bits = ix->sigF * ix->D;
   return FPP_OK;
 }
 
@@ -811,6 +852,10 @@ int fpp_debug_export_store(const fpp_index* ix, int32_t store, void* codes_out, 
     FPP_HIP(hipMemcpy2DAsync(codes_out, (size_t)ix->d, ix->Xfp8, (size_t)ix->ld8, (size_t)ix->d,
                              (size_t)ix->n, hipMemcpyDeviceToDevice, s));
     FPP_HIP(hipMemcpyAsync(scales_out, ix->fp8_scale, (size_t)ix->n * 4, hipMemcpyDeviceToDevice, s));
+  } else if (store == FPP_STORE_SIMHASH) {
+    const size_t words = ((size_t)ix->sigF * ix->D + 31) / 32;
+    FPP_HIP(hipMemcpy2DAsync(codes_out, words * 4, ix->Xsig, (size_t)ix->ldsig * 4, words * 4,
+                             (size_t)ix->n, hipMemcpyDeviceToDevice, s));
   } else {
     return set_error("store %d has no low-precision copy", store), FPP_EINVAL;
   }

@@ -64,6 +64,9 @@ struct fpp_index {
   uint8_t* Xfp8 = nullptr;        // device [n][ld8]
   float* fp8_scale = nullptr;     // device [n]
   float* center_vec = nullptr;    // device [d] centring vector (centred builds only)
+  uint32_t* Xsig = nullptr;       // device [n][ldsig] SimHash signatures
+  int32_t sigF = 0;               // hash functions in a signature
+  int32_t ldsig = 0;              // signature row stride in 32-bit words (multiple of 4)
   const float* Xh = nullptr;      // hashing input of the build kernels ([n][ldx]): X, or X - c
   uint32_t* sign_mask = nullptr;  // device [L][l][3][P]: 0 or 0x80000000 (xor mask of the sign)
   uint32_t* offsets = nullptr;    // device [L][NB + 1], absolute positions into ids
@@ -117,6 +120,10 @@ hipError_t launch_build_tables(const fpp_index* ix, int t0, int Tc, const BuildS
 
 // Quantised stores.
 hipError_t launch_quantize(const fpp_index* ix, hipStream_t s);
+// SimHash signature words of m vectors from their sorted lists lc [m][lf][D] (the first F
+// functions): out [m][ldsig], padding words zero.
+hipError_t launch_pack_signs(const uint16_t* lc, int64_t m, int lf, int D, int F, int ldsig,
+                             uint32_t* out, hipStream_t s);
 // Centred copy of X (ix->center_vec must be set): Xc [n][ldx].
 hipError_t launch_center(const fpp_index* ix, float* Xc, hipStream_t s);
 // Standard normal quantile (Wichura's algorithm AS 241, PPND16), 0 < p < 1.
@@ -187,7 +194,8 @@ struct Layout {
   int32_t short_ld = 0;   // short-list row length
   bool gbm = false;       // overflow bitmaps live in the scratch (else the caller provides them)
   int grid = 0;
-  size_t off_la = 0, off_lc = 0, off_probes = 0, off_np = 0, off_short = 0, off_gbm = 0, total = 0;
+  size_t off_la = 0, off_lc = 0, off_probes = 0, off_np = 0, off_short = 0, off_qsig = 0, off_gbm = 0,
+         total = 0;
 };
 
 size_t a256(size_t v);

@@ -5,6 +5,8 @@
 // unnormalised Walsh-Hadamard transform" (stage h = 1, 2, ..., P/2; the lower element of a pair
 // becomes a + b, the upper a - b) and reads the first D outputs y_i. Sign flips are XORs of the
 // sign bit; there are no multiplications, so the float32 results are those of that order.
+#include <algorithm>
+
 #include "fpp_internal.hpp"
 #include "lanes.hpp"
 
@@ -363,7 +365,42 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
   }
 }
 
+// One thread per (vector, signature word): scans the sorted lists of the functions the word
+// covers and sets bit i of function g when the code at some position is i + D (y_i < 0).
+__global__ __launch_bounds__(256) void pack_signs_kernel(const uint16_t* __restrict__ lc, int64_t m,
+                                                         int lf, int D, int F, int ldsig,
+                                                         uint32_t* __restrict__ out) {
+  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (x >= m * ldsig) return;
+  const int64_t v = x / ldsig;
+  const int w = (int)(x - v * ldsig);
+  const int64_t b0 = (int64_t)w * 32;
+  uint32_t word = 0u;
+  if (b0 < (int64_t)F * D) {
+    const int g0 = (int)(b0 / D);
+    const int g1 = (int)std::min<int64_t>(F - 1, (b0 + 31) / D);
+    for (int g = g0; g <= g1; ++g) {
+      const uint16_t* row = lc + ((size_t)v * lf + g) * D;
+      for (int p = 0; p < D; ++p) {
+        const int c = row[p];
+        const int64_t b = (int64_t)g * D + (c - D) - b0;   // bit of index c - D, for c >= D
+        if (c >= D && b >= 0 && b < 32) word |= 1u << b;
+      }
+    }
+  }
+  out[x] = word;
+}
+
 }  // namespace
+
+hipError_t launch_pack_signs(const uint16_t* lc, int64_t m, int lf, int D, int F, int ldsig,
+                             uint32_t* out, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  const int64_t tot = m * ldsig;
+  hipLaunchKernelGGL(pack_signs_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, lc, m,
+                     lf, D, F, ldsig, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_bucket,
                              float* rec_key, hipStream_t s) {

@@ -50,6 +50,10 @@ template <>
 struct Elems<FPP_STORE_FP8> {
   static constexpr int kPerChunk = 16;
 };
+template <>
+struct Elems<FPP_STORE_SIMHASH> {
+  static constexpr int kPerChunk = 4;   // 32-bit signature words; the query row holds its words
+};
 
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
@@ -80,6 +84,11 @@ __device__ __forceinline__ float fold_chunk(float p, const float* qv, uint4 w) {
       p = __fmaf_rn(qv[2 * i], bf16_lo(ws[i]), p);
       p = __fmaf_rn(qv[2 * i + 1], bf16_hi(ws[i]), p);
     }
+  } else if constexpr (STORE == FPP_STORE_SIMHASH) {
+    // Hamming distance to the query's signature words (small integers, exact in float)
+    const int h = __popc(w.x ^ __float_as_uint(qv[0])) + __popc(w.y ^ __float_as_uint(qv[1])) +
+                  __popc(w.z ^ __float_as_uint(qv[2])) + __popc(w.w ^ __float_as_uint(qv[3]));
+    p += (float)h;
   } else {
     const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
@@ -309,6 +318,7 @@ struct ScoreParams {
   int64_t* stats;
   uint32_t* gbitmap;         // [gridDim.x][bm_words], zero on entry and on exit
   int64_t bm_words;
+  float sig_bits;            // SimHash: bits per signature
 };
 
 struct SharedState {
@@ -442,6 +452,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       const int32_t myid = myrow < rows ? (int32_t)queue[myrow] : -1;
       float s = part[0];
       if constexpr (STORE == FPP_STORE_FP8) s = s * scl;
+      if constexpr (STORE == FPP_STORE_SIMHASH) s = p.sig_bits - 2.0f * s;   // F*D - 2 Hamming
       const uint64_t key = make_key(s, myid);
       const bool pass = reports_row<G, U>(g) && myid >= 0 && key > thr;
       const uint64_t mask = __ballot(pass);
@@ -754,6 +765,15 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
       sp.nchunks = ix->ld8 / 16;
       sp.scale = ix->fp8_scale;
       return dispatch_store<FPP_STORE_FP8>(sp, grid, s);
+    case FPP_STORE_SIMHASH:
+      // the query rows (a.Q, a.ldq) are signature words; F * D <= 1024 bits: 8 chunks at most
+      if (ix->ldsig > 32) return hipErrorInvalidValue;
+      sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xsig);
+      sp.ld_bytes = (int64_t)ix->ldsig * 4;
+      sp.nchunks = ix->ldsig / 4;
+      sp.d = ix->ldsig;
+      sp.sig_bits = (float)(ix->sigF * ix->D);
+      return launch_score_t<FPP_STORE_SIMHASH, 8, 1>(sp, grid, s);
     default:
       return hipErrorInvalidValue;
   }

@@ -573,6 +573,37 @@ def test_rerank_of_exactly_k_is_a_reorder_with_exact_scores():
 
 
 # ----------------------------------------------------------------------------------------------
+# SimHash pre-scoring
+@pytest.mark.parametrize("D,nf,l", [(32, 8, 2), (128, 2, 2), (16, 6, 1)])
+def test_simhash_store_and_queries(D, nf, l):
+    X, Q = synthdata.clustered_sphere(5_000, 64, 25, 10, 0.4, seed=33)
+    L = max(4, -(-nf // l))
+    oi = O.build_index(X, L, D, 0.4, 3, SEED, l=l)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    h = F().fpp_build_index(Xd, L, D, 0.4, 3, SEED, l=l, stores=("simhash",), simhash_functions=nf)
+    try:
+        assert F().fpp_index_get_info(h)["simhash_bits"] == nf * D
+        bits = O.simhash_bits(X, oi.signs, D, nf)
+        codes, _ = F().fpp_debug_export_store(h, "simhash")
+        np.testing.assert_array_equal(codes.cpu().numpy().view(np.uint32), O.simhash_words(bits))
+        qp = 6 * L
+        # the approximate pass itself: integer scores, ordered (score desc, id asc) -> exact
+        ai, asc = F().fpp_query(h, Qd, 10, qp, store="simhash", rerank_R=-1)
+        qbits = O.simhash_bits(Q, oi.signs, D, nf)
+        for r in range(Q.shape[0]):
+            cand = O.candidates(oi, O.probes(oi, Q[r], qp))
+            ri, rs = O.topk_order(O.simhash_score(bits[cand], qbits[r]), cand, 10)
+            assert np.array_equal(ai.cpu().numpy()[r], ri.astype(np.int32)), r
+            assert np.array_equal(asc.cpu().numpy()[r], rs.astype(np.float32)), r
+        # with the FP32 rerank of a short list of 100
+        ids, sc = F().fpp_query(h, Qd, 10, qp, store="simhash", rerank_R=100)
+        oids, osc, _ = O.query_reranked(oi, Q, 10, qp, R=100, storage="simhash", simhash_functions=nf)
+        assert check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 64) <= 3
+    finally:
+        F().fpp_free_index(h)
+
+
+# ----------------------------------------------------------------------------------------------
 @pytest.mark.timeout(600)
 def test_full_size_c2_sampled():
     """n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3, in the launch

@@ -342,6 +342,60 @@ def test_threshold_zero_keeps_every_record():
         assert np.array_equal(a.offsets[t], b.offsets[t]) and np.array_equal(a.ids[t], b.ids[t])
 
 
+# ------------------------------------------------------------------ SimHash store
+def test_simhash_bits_agree_with_the_hash_codes():
+    """The sign bit of a function's top index is set exactly when its code is i + D (Eq. 1)."""
+    X = _uniform_data(300, 32, 70)
+    S = O.rotation_signs(3, 2, 2, 32)
+    bits = O.simhash_bits(X, S, 32, 4)
+    for g in range(4):
+        t, f = divmod(g, 2)
+        h = O.hash_lists(X, S[t, f], 32)
+        top = h.idx[:, 0]
+        assert np.array_equal(bits[np.arange(300), g * 32 + top], h.code[:, 0] >= 32)
+
+
+def test_simhash_hamming_estimates_the_angle():
+    """For random rotations the fraction of differing signs estimates angle / pi (SimHash)."""
+    rng = np.random.default_rng(71)
+    d, F, D = 64, 16, 64
+    S = O.rotation_signs(9, F, 1, d)
+    for cos in (0.9, 0.5, 0.0):
+        fr = []
+        for _ in range(40):
+            a = rng.standard_normal(d)
+            a /= np.linalg.norm(a)
+            z = rng.standard_normal(d)
+            z -= (z @ a) * a
+            z /= np.linalg.norm(z)
+            b = cos * a + math.sqrt(1 - cos * cos) * z
+            bits = O.simhash_bits(np.stack([a, b]), S, D, F)
+            fr.append(np.mean(bits[0] != bits[1]))
+        assert abs(np.mean(fr) - math.acos(cos) / math.pi) < 0.04, (cos, np.mean(fr))
+
+
+def test_simhash_score_extremes_and_packing():
+    X = _uniform_data(20, 16, 72)
+    S = O.rotation_signs(4, 2, 2, 16)
+    bits = O.simhash_bits(X, S, 16, 4)
+    neg = O.simhash_bits(-X, S, 16, 4)
+    assert np.all(O.simhash_score(bits, bits[0])[0] == 64)
+    assert O.simhash_score(neg[:1], bits[0])[0] == -64          # every sign flips
+    w = O.simhash_words(bits)
+    for r in range(3):
+        for b in range(64):
+            assert ((int(w[r, b // 32]) >> (b % 32)) & 1) == int(bits[r, b])
+
+
+def test_simhash_rerank_with_full_short_list_equals_plain_query():
+    X = _uniform_data(400, 16, 73)
+    idx = O.build_index(X, L=3, D=8, alpha=0.5, iProbes=2, seed=12, l=2)
+    Q = _uniform_data(5, 16, 74)
+    ids, sc, _ = O.query_reranked(idx, Q, 5, 40, R=400, storage="simhash", simhash_functions=4)
+    pid, psc, _ = O.query(idx, Q, 5, 40)
+    assert np.array_equal(ids, pid)
+
+
 # ------------------------------------------------------------------ query
 def _brute_probes(idx, q, qProbes, gap=False):
     D, L = idx.D, idx.L
