@@ -118,6 +118,60 @@ def precision_report(torch, F, h, Xd, Qs, truth, k, qp, stores=("bf16", "fp8")):
     return out
 
 
+def variant_report(torch, F, w, Xd, Qd, truth, k, steps, warmup):
+    """The paper's heuristics and comparison methods on the same data and queries: for each,
+    build time, index size, the smallest swept qProbes with recall@10 >= 0.9 and the query
+    rate there."""
+    variants = {
+        "falconn_gap_probing": dict(build=dict(alpha=1.0, iProbes=1), query=dict(probe_score="gap")),
+        "falconnpp_gap_probing": dict(build={}, query=dict(probe_score="gap")),
+        "center_limit_scaling_k20": dict(build=dict(center=True, kappa=20), query={}),
+        "lsf_global_threshold": dict(build=dict(filter="threshold"), query={}),
+        "simhash_256_rerank100": dict(build=dict(stores=("simhash",)), query=dict(store="simhash")),
+        "simhash_1024_rerank512": dict(build=dict(stores=("simhash",), simhash_functions=8),
+                                       query=dict(store="simhash", rerank_R=512)),
+    }
+    out = {}
+    for name, v in variants.items():
+        b = dict(alpha=w.alpha, iProbes=w.iProbes)
+        b.update(v["build"])
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        h = F.fpp_build_index(Xd, w.L, w.D, b.pop("alpha"), b.pop("iProbes"), 42, l=w.l, **b)
+        torch.cuda.synchronize()
+        bs = time.perf_counter() - t
+        info = F.fpp_index_get_info(h)
+        rec = {}
+        chosen = None
+        for qp in QP_SWEEP:
+            ids, _ = F.fpp_query(h, Qd, k, qp, **v["query"])
+            r = recall_at_10(ids.cpu().numpy(), truth)
+            rec[str(qp)] = round(r, 4)
+            if r >= 0.9:
+                chosen = qp
+                break
+        res = {"build_s": round(bs, 3), "index_ids": info["total_ids"], "recall_sweep": rec, "qProbes": chosen}
+        if chosen is not None:
+            stage = np.zeros(4)
+            for _ in range(warmup):
+                F.fpp_query(h, Qd, k, chosen, **v["query"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            tot = np.zeros(4)
+            for _ in range(steps):
+                F.fpp_query(h, Qd, k, chosen, stage_ms=stage, **v["query"])
+                tot += stage
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / steps
+            res.update(qps=round(Qd.shape[0] / (ms / 1e3), 1), ms_per_call=round(ms, 3),
+                       stage_ms=[round(x, 4) for x in tot / steps])
+        F.fpp_free_index(h)
+        out[name] = res
+        log(f"variant {name}: build {bs:.3f}s ids {info['total_ids']} qProbes {chosen} "
+            f"recall {rec.get(str(chosen))} qps {res.get('qps')}")
+    return out
+
+
 def timed_steps(torch, F, h, Qd, k, qp, store, steps, warmup):
     """Mean wall ms per step over the timed steps (one bracket), the median step, and the mean
     per-stage event times (hash, probe selection, gather/score/top-k, rerank)."""
@@ -304,6 +358,8 @@ def main():
     ap.add_argument("--qprobes", type=int, default=0, help="total probes per query (0 = sweep for recall >= 0.9)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the heuristics / comparison-method report")
     ap.add_argument("--serving-seconds", type=float, default=10.0,
                     help="duration per offered load (at most 100,000 queries per load)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -383,6 +439,8 @@ def main():
                           unique=float(st[:, 2].mean()))
         log(f"{store}: {ms:.3f} ms/step {res[store]['qps']:.0f} q/s stages {stage.round(3)} "
             f"gather {res[store]['gbs']:.0f} GB/s unique/q {res[store]['unique']:.0f}")
+
+    variants = None if args.no_variants else variant_report(torch, F, w, Xd, Qd, truth, k, args.steps, args.warmup)
 
     serving = {}
     sustained = None
@@ -465,6 +523,7 @@ def main():
         "fp8_batch": {"qps": round(res["fp8"]["qps"], 1), "ms_per_step": round(res["fp8"]["ms_per_step"], 4),
                       "stage_ms": res["fp8"]["stage_ms"], "gather_gbs": round(res["fp8"]["gbs"], 1)},
         "precision": precision,
+        "variants": variants,
         "serving": {"sustained_qps": ser.get("offered_qps"), "load": ser.get("load"),
                     "p50_ms": ser.get("p50_ms"), "p99_ms": ser.get("p99_ms"),
                     "achieved_qps": ser.get("achieved_qps"), "loads": serving},
