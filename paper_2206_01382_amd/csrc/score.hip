@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       if (mask) {
         uint32_t basepos = 0;
         if (lane == 0) basepos = atomicAdd(&st->ccount, (uint32_t)__popcll(mask));
-        basepos = __shfl(basepos, 0);
+        basepos = __builtin_amdgcn_readfirstlane(basepos);
         if (pass) cand[basepos + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = key;
       }
     };
@@ -559,22 +559,23 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
             fresh |= f ? (1u << u) : 0u;
           }
         }
-        // enqueue first occurrences (wave prefix sum of per-lane counts)
-        const uint32_t cnt = (uint32_t)__popc(fresh);
-        uint32_t inc = cnt;
+        // enqueue first occurrences in lane-major order: one ballot per entry slot gives every
+        // lane the count of fresh entries of the lanes below it
+        const uint64_t below = (1ull << lane) - 1ull;
+        uint32_t before = 0, wtot = 0;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-          const uint32_t t = __shfl_up(inc, o);
-          if (lane >= o) inc += t;
+        for (int u = 0; u < kEPT; ++u) {
+          const uint64_t mk = __ballot((fresh >> u) & 1u);
+          before += (uint32_t)__popcll(mk & below);
+          wtot += (uint32_t)__popcll(mk);
         }
-        const uint32_t wtot = __shfl(inc, 63);
         uint32_t basepos = 0;
-        if (lane == 63 && wtot) {
+        if (lane == 0 && wtot) {
           basepos = atomicAdd(&st->qcount, wtot);
           atomicAdd(&st->uniq, wtot);
         }
-        basepos = __shfl(basepos, 63);
-        uint32_t pos = basepos + inc - cnt;
+        basepos = __builtin_amdgcn_readfirstlane(basepos);
+        uint32_t pos = basepos + before;
 #pragma unroll
         for (int u = 0; u < kEPT; ++u)
           if (fresh & (1u << u)) queue[pos++] = (uint32_t)idv[u];
