@@ -16,6 +16,7 @@
 #include <algorithm>
 
 #include "fpp_internal.hpp"
+#include "lanes.hpp"
 
 namespace fpp {
 namespace {
@@ -86,7 +87,7 @@ __device__ __forceinline__ uint64_t count_table(const Lists& ls, int t, int l, f
 __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  for (int o = 32; o > 0; o >>= 1) v += xor_lanes_n(v, o);
   if (lane == 0) red[w] = v;
   __syncthreads();
   uint64_t t = 0;
@@ -99,7 +100,7 @@ __device__ __forceinline__ uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
 __device__ __forceinline__ float block_max(float v, float* red) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, xor_lanes_n(v, o));
   if (lane == 0) red[w] = v;
   __syncthreads();
   float t = red[0];
