@@ -43,6 +43,34 @@ struct QLayout {
   static constexpr int IPW = 64 / LPI;                              // items per wavefront
 };
 
+// v + (v of lane ^ X) * mul. For X = 1, 2 and 8 the partner is a DPP operand of one v_fmac (quad
+// permutes, and a rotation by 8 within a 16-lane row); the s_nop gives the two wait states a DPP
+// read needs after a VALU write of its source. Other distances go through xor_lanes.
+template <int X>
+__device__ __forceinline__ float fmac_xor(float v, float mul) {
+  float src = v;
+  if constexpr (X == 1) {
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
+  } else if constexpr (X == 2) {
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
+  } else if constexpr (X == 8) {
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:8 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
+  } else {
+    v = __builtin_fmaf(xor_lanes<X>(v), mul, v);
+  }
+  return v;
+}
+__device__ __forceinline__ float fmac_xor_n(float v, int x, float mul) {
+  switch (x) {
+    case 1: return fmac_xor<1>(v, mul);
+    case 2: return fmac_xor<2>(v, mul);
+    case 4: return fmac_xor<4>(v, mul);
+    case 8: return fmac_xor<8>(v, mul);
+    case 16: return fmac_xor<16>(v, mul);
+    default: return fmac_xor<32>(v, mul);
+  }
+}
+
 // Exact 64-bit list key: |y| bits << 32 | (0xffff - i) << 1 | sign; descending order of keys is
 // (|y| desc, i asc), and the low bit carries the code (i or i + D).
 __device__ __forceinline__ uint64_t exact_key(float y, int i) {
@@ -275,7 +303,7 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
     for (int hl = 1; hl < LPI; hl <<= 1) {
       const float mul = (li & hl) ? -1.0f : 1.0f;
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = __builtin_fmaf(xor_lanes_n(v[e], hl), mul, v[e]);
+      for (int e = 0; e < E; ++e) v[e] = fmac_xor_n(v[e], hl, mul);
     }
   }
 #pragma unroll
