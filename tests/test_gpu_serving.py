@@ -133,3 +133,29 @@ def test_overlapping_batches_on_several_streams(env):
     for (row, m, k, qp), (ids, sc) in zip(reqs[::20], outs[::20]):
         ri, rs = F.fpp_query(h, Qd[row:row + m].contiguous(), k, qp)
         assert torch.equal(ids, ri) and torch.equal(sc, rs)
+
+
+@pytest.mark.parametrize("store,probe_score", [("fp32", "gap"), ("simhash", "sum"), ("bf16", "gap")])
+def test_served_options_equal_direct_queries(env, store, probe_score):
+    """The server passes the store and the probe score through: each request equals the direct
+    query with the same options."""
+    F, h, Xd, Qd = env
+    hh = h
+    if store == "simhash":
+        hh = F.fpp_build_index(Xd, 8, 32, 0.3, 3, 77, l=2, stores=("simhash",))
+    try:
+        rng = np.random.default_rng(4)
+        reqs = _requests(rng, Qd.shape[0], 60, (1, 10), (8, 40, 200))
+        sv = F.fpp_server_create(hh, scratch_bytes=256 << 20, n_streams=2, max_batch=64, store=store,
+                                 probe_score=probe_score)
+        try:
+            outs, stamps, _ = _run(F, sv, Qd, reqs, 10)
+        finally:
+            F.fpp_server_destroy(sv)
+        for (row, m, k, qp), (ids, sc), (status, ts, td) in zip(reqs, outs, stamps):
+            assert status == 0
+            ri, rs = F.fpp_query(hh, Qd[row:row + m].contiguous(), k, qp, store=store, probe_score=probe_score)
+            assert torch.equal(ids, ri) and torch.equal(sc, rs)
+    finally:
+        if hh is not h:
+            F.fpp_free_index(hh)
