@@ -694,13 +694,15 @@ hipError_t launch_score_t(const ScoreParams& sp, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
-// (G, C) per store and chunk count: G = lanes per row (power of two), C = chunks per lane.
+// (G, C) per store and chunk count: G = lanes per row (power of two), C = chunks per lane. Up to
+// 32 chunks (512 bytes) a row takes 8 lanes: each load instruction still covers whole 128-byte
+// lines of a row, and fewer lanes per row mean fewer reduction levels and address computations.
 template <int STORE>
 hipError_t dispatch_store(const ScoreParams& sp, int grid, hipStream_t s) {
   const int nc = sp.nchunks;
   if (nc <= 8) return launch_score_t<STORE, 8, 1>(sp, grid, s);
-  if (nc <= 16) return launch_score_t<STORE, 16, 1>(sp, grid, s);
-  if (nc <= 32) return launch_score_t<STORE, 32, 1>(sp, grid, s);
+  if (nc <= 16) return launch_score_t<STORE, 8, 2>(sp, grid, s);
+  if (nc <= 32) return launch_score_t<STORE, 8, 4>(sp, grid, s);
   if (nc <= 64) return launch_score_t<STORE, 64, 1>(sp, grid, s);
   if (nc <= 128) return launch_score_t<STORE, 64, 2>(sp, grid, s);
   if (nc <= 256) return launch_score_t<STORE, 64, 4>(sp, grid, s);
@@ -790,9 +792,9 @@ hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m
   hipLaunchKernelGGL((rerank_kernel<GG, CC>), dim3((unsigned)m), dim3(256), 0, s, ix->X,       \
                      (int64_t)ix->ldx, nc, ix->d, Q, ldq, m, short_ids, short_ld, k_arr,        \
                      k_uniform, R_opt, out_off, ids_out, scores_out)
-  if (nc <= 8) FPP_RERANK(8, 1);
-  else if (nc <= 16) FPP_RERANK(16, 1);
-  else if (nc <= 32) FPP_RERANK(32, 1);
+  if (nc <= 8) FPP_RERANK(8, 1);      // the FP32 gather's (G, C) for the same chunk count
+  else if (nc <= 16) FPP_RERANK(8, 2);
+  else if (nc <= 32) FPP_RERANK(8, 4);
   else if (nc <= 64) FPP_RERANK(64, 1);
   else if (nc <= 128) FPP_RERANK(64, 2);
   else if (nc <= 256) FPP_RERANK(64, 4);

@@ -85,9 +85,11 @@ EPC = {"fp32": 4, "bf16": 8, "fp8": 16}     # elements per 16-byte chunk of a st
 def lane_layout(d, store="fp32"):
     """(G lanes per row, C chunks per lane) of the gather kernel for rows of d elements."""
     nc = -(-d // EPC[store])
-    for G in (8, 16, 32, 64):
-        if nc <= G:
-            return G, 1
+    for C in (1, 2, 4):
+        if nc <= 8 * C:
+            return 8, C
+    if nc <= 64:
+        return 64, 1
     return 64, (2 if nc <= 128 else 4)
 
 
