@@ -352,7 +352,7 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
     FPP_TRY(sg.get(&lc, (size_t)std::min(rows, n) * sigF * D));
     for (int64_t r0 = 0; r0 < n; r0 += rows) {
       const int64_t nr = std::min(rows, n - r0);
-      FPP_HIP(launch_hash_query(&view, ix->X + r0 * ix->ldx, nr, ix->ldx, la, lc, s));
+      FPP_HIP(launch_hash_query(&view, ix->X + r0 * ix->ldx, nr, ix->ldx, la, lc, view.D, s));
       FPP_HIP(launch_pack_signs(lc, nr, sigF, D, sigF, ix->ldsig, ix->Xsig + r0 * ix->ldsig, s));
     }
     FPP_HIP(hipStreamSynchronize(s));
@@ -449,7 +449,9 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     const int64_t mc = std::min<int64_t>(ly.mc, qs.m - c0);
     const float* Qc = qs.Q + c0 * d;
     FPP_TRY(mark());
-    FPP_HIP(launch_hash_query(ix, Qc, mc, d, la, lc, s));
+    // the SimHash signature reads every code; probe selection only a prefix of each list
+    const int W = qs.store == FPP_STORE_SIMHASH ? ix->D : probe_list_len(ix, ly.qcap);
+    FPP_HIP(launch_hash_query(ix, Qc, mc, d, la, lc, W, s));
     FPP_TRY(mark());
     FPP_HIP(launch_probe_select(ix, la, lc, mc, qs.qp_dev ? qs.qp_dev + c0 : nullptr, qs.qp_uniform,
                                 ly.qcap, qs.probe_score, probes, np, s));
@@ -744,7 +746,7 @@ int fpp_debug_query_lists(const fpp_index* ix, const float* V, int64_t m, float*
   DeviceScratch sc;
   uint16_t* lc = nullptr;
   FPP_TRY(sc.get(&lc, cnt));
-  FPP_HIP(launch_hash_query(ix, V, m, ix->d, abs_out, lc, s));
+  FPP_HIP(launch_hash_query(ix, V, m, ix->d, abs_out, lc, ix->D, s));
   std::vector<uint16_t> h(cnt);
   FPP_HIP(hipMemcpyAsync(h.data(), lc, cnt * 2, hipMemcpyDeviceToHost, s));
   FPP_HIP(hipStreamSynchronize(s));
@@ -820,7 +822,7 @@ int fpp_debug_probes(const fpp_index* ix, const float* Q, int64_t m, int32_t qPr
   FPP_TRY(sc.get(&lc, (size_t)m * LFD));
   FPP_TRY(sc.get(&pr, (size_t)m * qcap));
   FPP_TRY(sc.get(&np, (size_t)m));
-  FPP_HIP(launch_hash_query(ix, Q, m, ix->d, la, lc, s));
+  FPP_HIP(launch_hash_query(ix, Q, m, ix->d, la, lc, probe_list_len(ix, qcap), s));
   FPP_HIP(launch_probe_select(ix, la, lc, m, nullptr, qProbes, qcap, probe_score, pr, np, s));
   std::vector<uint32_t> h((size_t)m * qcap);
   std::vector<int32_t> hn((size_t)m);

@@ -97,9 +97,10 @@ hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_
                              float* rec_key, hipStream_t s);
 
 // Query-side hash: sorted lists for m vectors (row stride ldv floats) and all L*l functions.
-//   la: [m][L*l][D] float32, lc: [m][L*l][D] uint16 codes.
+//   la: [m][L*l][D] float32, lc: [m][L*l][D] uint16 codes. Entries [0, W) of every list are
+//   written (1 <= W <= D; the kernel may write up to a multiple of its per-lane run past W).
 hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int ldv, float* la,
-                             uint16_t* lc, hipStream_t s);
+                             uint16_t* lc, int W, hipStream_t s);
 
 // Per-table build passes over a chunk of Tc tables.
 struct BuildScratch {
@@ -130,7 +131,8 @@ hipError_t launch_center(const fpp_index* ix, float* Xc, hipStream_t s);
 double normal_quantile(double p);
 
 // Probe selection: probes [m][qcap] as absolute offset-array positions t * (NB + 1) + bucket;
-// nprobe[m] receives the count per query.
+// nprobe[m] receives the count per query. It reads list entries [0, probe_list_len) only.
+int probe_list_len(const fpp_index* ix, int32_t qcap);
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc,
                                int64_t m, const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
                                int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s);

@@ -216,11 +216,12 @@ __device__ __forceinline__ bool out_of_order(const uint64_t (&key)[E], int j0, i
 }
 
 // VEC: rows of V are 16-byte aligned and d % 4 == 0. FULL: D == P (every output is listed), which
-// turns the per-element bounds tests into constants.
+// turns the per-element bounds tests into constants. Only the first W entries of each sorted list
+// are stored (rounded up to the E entries of a lane; W = D stores all).
 template <int P, bool VEC, bool FULL>
 __global__ __launch_bounds__(256) void hash_query_kernel(
     const float* __restrict__ V, uint32_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
-    int LF, int D_arg, float* __restrict__ la, uint16_t* __restrict__ lc) {
+    int LF, int D_arg, int W, float* __restrict__ la, uint16_t* __restrict__ lc) {
   const int D = FULL ? P : D_arg;
   constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI, IPW = QLayout<P>::IPW;
   const int lane = threadIdx.x & 63;
@@ -356,7 +357,7 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
     for (int e = 0; e < E; ++e)
       if (j0 + e < D) key[e] = slot[j0 + e];
   }
-  if (!valid) return;
+  if (!valid || j0 >= W) return;
   float* ola = la + (size_t)item * D;
   uint16_t* olc = lc + (size_t)item * D;
   uint32_t av[E], cv[E];
@@ -444,8 +445,9 @@ hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_
 }
 
 hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int ldv, float* la,
-                             uint16_t* lc, hipStream_t s) {
+                             uint16_t* lc, int W, hipStream_t s) {
   if (m <= 0) return hipSuccess;
+  if (W < 1 || W > ix->D) return hipErrorInvalidValue;
   const int LF = ix->L * ix->l;
   const int64_t items = m * LF;
   if (items >= (int64_t)1 << 31) return hipErrorInvalidValue;   // callers chunk the queries
@@ -453,7 +455,7 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
   const bool full = ix->D == ix->P;
 #define FPP_HQ_LAUNCH(PP, VV, FF)                                                              \
   hipLaunchKernelGGL((hash_query_kernel<PP, VV, FF>), grid, dim3(256), lds, s, V, (uint32_t)m,   \
-                     ldv, ix->d, ix->sign_mask, LF, ix->D, la, lc)
+                     ldv, ix->d, ix->sign_mask, LF, ix->D, W, la, lc)
 #define FPP_HQ(PP)                                                                             \
   case PP: {                                                                                   \
     const int64_t waves = (items + QLayout<PP>::IPW - 1) / QLayout<PP>::IPW;                   \

@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
       je = jg;
       while (je < D && pair_score(a0, ls.get(lb_, je), off) >= tau_eq) ++je;
     }
-    for (int i = 0; i < D && (jg > 0 || je > 0); ++i) {
+    for (int i = 0; i < D && (jg > 0 || (je > 0 && te < need)); ++i) {
       const float ai = ls.get(la_, i);
       while (jg > 0 && !(pair_score(ai, ls.get(lb_, jg - 1), off) >= thr_gt)) --jg;
       if (need)
@@ -330,6 +330,16 @@ int probe_prefix(const fpp_index* ix, int32_t qcap) {
   if (want > ix->D) want = ix->D;
   while (want > 1 && (LF * (want + 1) + ix->L + 1) * 4 > 60 * 1024) want >>= 1;
   return want;
+}
+
+// List entries the selection can need: every selected pair (i, j) of a query with qP <= qcap
+// probes has (i + 1)(j + 1) <= qP, and the count walks read positions <= qP only (they stop at a
+// count of qP + 1). The emission walk reads further only once the table has nothing left to
+// emit, where the values it reads decide nothing. Positions [0, qcap + 2) and the LDS prefix are
+// therefore enough.
+int probe_list_len(const fpp_index* ix, int32_t qcap) {
+  const int64_t w = std::max<int64_t>((int64_t)qcap + 2, probe_prefix(ix, qcap));
+  return (int)std::min<int64_t>(w, ix->D);
 }
 
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc, int64_t m,
