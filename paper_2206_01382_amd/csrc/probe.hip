@@ -13,6 +13,10 @@
 //     (table, i, j) order until qProbes are selected.
 // One workgroup per query; thread x walks tables x, x + 128, ... with the first M entries of
 // every sorted list staged in LDS (entries past M are read from device memory).
+// When 4 qProbes <= L, a lower bound from the tables' best pairs usually leaves few candidate
+// pairs; a first kernel ranks those directly, and the bisection runs only for the queries where
+// it could not. (With more probes per table the candidates grow faster than the bisection's
+// cost, which is why the direct ranking is kept to this range.)
 #include <algorithm>
 
 #include "fpp_internal.hpp"
@@ -24,6 +28,8 @@ namespace {
 constexpr int kProbeThreads = 128;
 constexpr int kRankTables = 1024;   // rank the tables' best pairs for the lower bound up to this L
 constexpr int kProbeWaves = kProbeThreads / 64;
+constexpr int kDirectCap = 256;     // candidate pairs the sparse selection sorts in LDS
+constexpr int kDeepFloats = 3328;   // sparse selection: list entries staged per chunk of tables
 
 // Sorted-list access: the first M entries of every list of the query sit in LDS. List f of table
 // t (list index l * t + f) is LDS row f * L + t with a row stride of M + 1 words (M is a power of
@@ -132,16 +138,215 @@ __device__ __forceinline__ uint64_t block_scan_u64(uint64_t v, uint64_t& total, 
   return before + inc - v;
 }
 
-// One workgroup per query; thread x walks tables x, x + 128, ...
+// Emits the candidates of one table for the sparse selection: pairs (i, j) with score >= tau and
+// (i + 1)(j + 1) <= qP, from the table's staged list prefixes A and B (positions < lim =
+// min(qP, D)). Each goes to the next free slot of `key` (while slots remain; `count` keeps
+// counting) as order-preserving score bits << 32 | ~(t * R + i * D + j), R = D^l, so that a larger
+// key ranks first in (score desc, table asc, i asc, j asc) order.
+__device__ __forceinline__ void emit_region(const float* A, const float* B, int l, int D, int lim,
+                                            uint32_t qP, float tau, bool gap, uint32_t pos0,
+                                            uint64_t* key, uint32_t* count) {
+  if (l == 1) {
+    const float off = gap ? A[0] : 0.0f;
+    for (int c = 0; c < lim; ++c) {
+      const float sc = A[c] - off;
+      if (!(sc >= tau)) break;
+      const uint32_t p = atomicAdd(count, 1u);
+      if (p < (uint32_t)kDirectCap) key[p] = ((uint64_t)ord_of(sc) << 32) | (uint32_t)~(pos0 + (uint32_t)c);
+    }
+    return;
+  }
+  const float off = gap ? A[0] + B[0] : 0.0f;
+  const float a0 = A[0];
+  int j = 0;
+  while (j < lim && pair_score(a0, B[j], off) >= tau) ++j;
+  for (int i = 0; i < lim && j > 0; ++i) {
+    const float ai = A[i];
+    while (j > 0 && !(pair_score(ai, B[j - 1], off) >= tau)) --j;
+    const int r = (int)(qP / (uint32_t)(i + 1));
+    const int n = j < r ? j : r;
+    for (int jj = 0; jj < n; ++jj) {
+      const uint32_t p = atomicAdd(count, 1u);
+      if (p < (uint32_t)kDirectCap)
+        key[p] = ((uint64_t)ord_of(pair_score(ai, B[jj], off)) << 32) |
+                 (uint32_t)~(pos0 + (uint32_t)i * (uint32_t)D + (uint32_t)jj);
+    }
+  }
+}
+
+// Descending bitonic sort of n keys in LDS (n a power of two, at most 2 * kProbeThreads).
+__device__ __forceinline__ void probe_sort_desc(uint64_t* key, int n) {
+  for (int k = 2; k <= n; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n; i += kProbeThreads) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = key[i], b = key[ixj];
+          if ((i & k) == 0 ? (a < b) : (a > b)) {
+            key[i] = b;
+            key[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+}
+
+constexpr size_t sparse_lds_bytes(int L) {
+  return 64 + (size_t)kDirectCap * 8 + (size_t)kDeepFloats * 4 + (size_t)L * 8 + 8;
+}
+static_assert((64 + kDirectCap * 8) % 16 == 0, "staged lists must be 16-byte aligned");
+
+// Sparse selection, one workgroup per query with 4 qP <= L (others get nprobe = -1, as do queries
+// it cannot finish). The qP-th best of the tables' best pairs is a lower bound mn of the qP-th
+// best pair (the qP tables ranked at or above it each hold a pair scoring at least that). Only
+// tables whose best pair reaches mn can hold a selected pair, and only at positions with
+// (i + 1)(j + 1) <= qP, so those tables' first min(qP, D) list entries (rounded up to 4; D is a
+// multiple of 4) are staged in LDS a chunk of tables at a time and every pair of the region
+// scoring >= mn becomes a candidate. Sorted by key, the first qP candidates are the probes, in
+// rank order; only they read their bucket codes. Past kDirectCap candidates the query is left to
+// the bisection.
+__global__ __launch_bounds__(kProbeThreads) void probe_sparse_kernel(
+    const float* __restrict__ la, const uint16_t* __restrict__ lc, int64_t m, int L, int l, int D,
+    int64_t NB, const int32_t* __restrict__ qp_arr, int32_t qp_uniform, int32_t qcap, int gap_score,
+    uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
+  extern __shared__ __align__(16) unsigned char smem[];   // sparse_lds_bytes(L)
+  uint64_t* red = reinterpret_cast<uint64_t*>(smem);        // kProbeWaves words
+  uint64_t* dkey = reinterpret_cast<uint64_t*>(smem + 64);  // [kDirectCap] candidate keys
+  float* deep = reinterpret_cast<float*>(dkey + kDirectCap);   // [kDeepFloats] staged lists
+  float* tops = deep + kDeepFloats;                         // [L] best pair of every table
+  int32_t* act = reinterpret_cast<int32_t*>(tops + L);      // [L] tables reaching mn
+  float& sel = *reinterpret_cast<float*>(act + L);
+  uint32_t& count = *reinterpret_cast<uint32_t*>(act + L + 1);
+  const int64_t q = blockIdx.x;
+  if (q >= m) return;   // uniform
+  const int tid = threadIdx.x;
+  const int LF = L * l;
+  const float* Aq = la + (size_t)q * LF * D;
+  const uint16_t* Cq = lc + (size_t)q * LF * D;
+  const bool gap = gap_score != 0;
+  const uint64_t total = (uint64_t)L * (l == 1 ? (uint64_t)D : (uint64_t)D * D);
+  const int64_t want = qp_arr ? qp_arr[q] : qp_uniform;
+  uint64_t qP = want < 1 ? 0 : ((uint64_t)want < total ? (uint64_t)want : total);
+  if (qP > (uint64_t)qcap) qP = (uint64_t)qcap;
+  const int lim = qP < (uint64_t)D ? (int)qP : D;        // positions a candidate can occupy
+  const int lim4 = (lim + 3) / 4;
+  const int per4 = l * lim4;                              // staged float4 per table
+  const uint32_t R = l == 1 ? (uint32_t)D : (uint32_t)D * (uint32_t)D;
+  if (qP == 0 || 4 * qP > (uint64_t)L || L > kRankTables || D % 4 != 0 || per4 * 4 > kDeepFloats ||
+      (uint64_t)L * R > 0xffffffffull) {
+    if (tid == 0) nprobe[q] = -1;
+    return;
+  }
+
+  // every table's best pair (position 0 of its lists)
+  for (int t = tid; t < L; t += kProbeThreads) {
+    float top;
+    if (l == 1) {
+      const float a0 = Aq[(size_t)t * D];
+      top = a0 - (gap ? a0 : 0.0f);
+    } else {
+      const float a0 = Aq[(size_t)(2 * t) * D], b0 = Aq[(size_t)(2 * t + 1) * D];
+      top = pair_score(a0, b0, gap ? a0 + b0 : 0.0f);
+    }
+    tops[t] = top;
+  }
+  if (tid == 0) count = 0u;
+  __syncthreads();
+  // mn: the best pair of the table of rank qP - 1 in (best pair desc, table asc) order
+  for (int t = tid; t < L; t += kProbeThreads) {
+    const float v = tops[t];
+    int r = 0;
+    for (int u = 0; u < L; ++u) {
+      const float w = tops[u];
+      r += (w > v || (w == v && u < t)) ? 1 : 0;
+    }
+    if ((uint64_t)r == qP - 1) sel = v;
+  }
+  __syncthreads();
+  const float mn = sel;
+  // tables whose best pair reaches mn, in table order
+  int A = 0;
+  for (int t0 = 0; t0 < L; t0 += kProbeThreads) {
+    const int t = t0 + tid;
+    const uint64_t f = (t < L && tops[t] >= mn) ? 1u : 0u;
+    uint64_t tot;
+    const uint64_t p = block_scan_u64(f, tot, red);
+    if (f) act[A + (int)p] = t;
+    A += (int)tot;
+  }
+  __syncthreads();
+  const int CH = kDeepFloats / (per4 * 4);                // tables per staged chunk
+  float4* deep4 = reinterpret_cast<float4*>(deep);
+  for (int k0 = 0; k0 < A; k0 += CH) {
+    const int nk = A - k0 < CH ? A - k0 : CH;
+    const int n4 = nk * per4;
+    for (int x0 = 0; x0 < n4; x0 += 8 * kProbeThreads) {
+      // eight loads in flight per thread (indices past the chunk reload its last entry, so the
+      // loads need no branch and stay in registers)
+      float4 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        int x = x0 + u * kProbeThreads + tid;
+        x = x < n4 ? x : n4 - 1;
+        const int k = x / per4, r = x - k * per4;
+        const int f = r / lim4, e4 = r - f * lim4;
+        const int t = act[k0 + k];
+        v[u] = *reinterpret_cast<const float4*>(Aq + (size_t)(l == 2 ? 2 * t + f : t) * D + 4 * e4);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int x = x0 + u * kProbeThreads + tid;
+        if (x < n4) deep4[x] = v[u];
+      }
+    }
+    __syncthreads();
+    for (int k = tid; k < nk; k += kProbeThreads) {
+      const int t = act[k0 + k];
+      const float* Ak = deep + k * per4 * 4;
+      emit_region(Ak, Ak + lim4 * 4, l, D, lim, (uint32_t)qP, mn, gap, (uint32_t)t * R, dkey, &count);
+    }
+    __syncthreads();
+  }
+  const uint32_t C = count;
+  if (C > (uint32_t)kDirectCap) {
+    if (tid == 0) nprobe[q] = -1;
+    return;
+  }
+  int n = 2;
+  while ((uint32_t)n < C) n <<= 1;
+  for (int c = (int)C + tid; c < n; c += kProbeThreads) dkey[c] = 0ull;
+  __syncthreads();
+  probe_sort_desc(dkey, n);
+  uint32_t* out = probes + (size_t)q * qcap;
+  const int64_t stride = NB + 1;
+  for (int r = tid; (uint64_t)r < qP; r += kProbeThreads) {
+    const uint32_t pos = ~(uint32_t)dkey[r];
+    const uint32_t t = pos / R, rem = pos - t * R;
+    const uint32_t tbase = (uint32_t)((int64_t)t * stride);
+    if (l == 1) {
+      out[r] = tbase + Cq[(size_t)t * D + rem];
+    } else {
+      const uint32_t i = rem / (uint32_t)D, j = rem - i * (uint32_t)D;
+      out[r] = tbase + (uint32_t)Cq[(size_t)(2 * t) * D + i] * (uint32_t)(2 * D) +
+               Cq[(size_t)(2 * t + 1) * D + j];
+    }
+  }
+  if (tid == 0) nprobe[q] = (int32_t)qP;
+}
+
+// One workgroup per query; thread x walks tables x, x + 128, ... With `skip_done`, queries whose
+// nprobe the sparse selection has already set (>= 0) are skipped.
 __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     const float* __restrict__ la, const uint16_t* __restrict__ lc, int64_t m, int L, int l, int D,
     int M, int64_t NB, const int32_t* __restrict__ qp_arr, int32_t qp_uniform, int32_t qcap,
-    int gap_score, uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
+    int gap_score, int skip_done, uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* red = reinterpret_cast<uint64_t*>(smem);        // kProbeWaves words
   float* pre = reinterpret_cast<float*>(smem + 64);         // [l][L][M + 1] list prefixes
   const int64_t q = blockIdx.x;
   if (q >= m) return;   // uniform
+  if (skip_done && nprobe[q] >= 0) return;
   const int tid = threadIdx.x;
   const int LF = L * l;
   const float* Aq = la + (size_t)q * LF * D;
@@ -353,8 +558,18 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  // the sparse selection first, where some query may qualify (4 qP <= L); the bisection then
+  // takes the queries it left (nprobe = -1)
+  const bool sparse = ix->L <= kRankTables && ix->D % 4 == 0 &&
+                      (qp_arr != nullptr || 4 * (int64_t)std::min(qp_uniform, qcap) <= ix->L);
+  if (sparse)
+    hipLaunchKernelGGL(probe_sparse_kernel, dim3((unsigned)m), dim3(kProbeThreads),
+                       sparse_lds_bytes(ix->L), s, la, lc, m,
+                       ix->L, ix->l, ix->D, ix->NB, qp_arr, qp_uniform, qcap, probe_score, probes,
+                       nprobe);
   hipLaunchKernelGGL(probe_kernel, dim3((unsigned)m), dim3(kProbeThreads), lds, s, la, lc, m, ix->L,
-                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probe_score, probes, nprobe);
+                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probe_score, sparse ? 1 : 0,
+                     probes, nprobe);
   return hipGetLastError();
 }
 

@@ -49,6 +49,11 @@ CONFIGS = {
                           centers=10, spread=0.4),
     "l1_D8_iprobes3": dict(kind="cl", n=1_500, d=12, L=4, D=8, l=1, alpha=0.6, iProbes=3, m=20,
                            centers=5, spread=0.5),
+    # many tables: probe totals up to L take the direct selection
+    "manyL_d24_L40": dict(kind="cl", n=3_000, d=24, L=40, D=16, l=2, alpha=0.4, iProbes=2, m=20,
+                          centers=10, spread=0.4),
+    "l1_L24_D16": dict(kind="cl", n=2_000, d=16, L=24, D=16, l=1, alpha=0.5, iProbes=2, m=20,
+                       centers=8, spread=0.5),
 }
 SEED = 1234
 
@@ -234,7 +239,9 @@ def test_tables_bit_exact(name):
 def test_probe_sets_bit_exact(name):
     w, oi, h, Xd, Qd = built(name)
     total = w["L"] * (w["D"] ** w["l"])
-    for qp in sorted({1, 17, 4 * w["L"], 50 * w["L"], total, total + 5}):
+    # totals up to L / 4 take the direct ranking of the sparse selection, larger ones the bisection
+    for qp in sorted({1, 2, 17, max(1, w["L"] // 4), max(1, w["L"] // 2), w["L"], 4 * w["L"], 50 * w["L"],
+                      total, total + 5}):
         g = F().fpp_debug_probes(h, Qd, qp).cpu().numpy()
         for r in range(w["Q"].shape[0]):
             ref = O.probes(oi, w["Q"][r], qp)
@@ -246,7 +253,7 @@ def test_gap_probe_sets_bit_exact(name):
     """Plain Falconn's gap score: probe sets bit-exact, and queries match the oracle."""
     w, oi, h, Xd, Qd = built(name)
     total = w["L"] * (w["D"] ** w["l"])
-    for qp in sorted({1, 3, w["L"], 4 * w["L"], 50 * w["L"], total}):
+    for qp in sorted({1, 3, max(1, w["L"] // 4), w["L"], 4 * w["L"], 50 * w["L"], total}):
         g = F().fpp_debug_probes(h, Qd, qp, probe_score="gap").cpu().numpy()
         for r in range(w["Q"].shape[0]):
             ref = O.probes(oi, w["Q"][r], qp, "gap")
