@@ -145,7 +145,10 @@ void fpp_default_query_opts(fpp_query_opts* opts);
  *   ids_out    device, int32 [m][k]: ids by (score desc, id asc); -1 pads short results.
  *   scores_out device, float32 [m][k]: FP32 inner products q^T x on the stored FP32 X
  *              (after a low-precision pass, the exact FP32 rerank scores); -inf pads.
- * Scratch memory is taken from the stream-ordered allocator on `stream`.
+ * Scratch memory is taken from the stream-ordered allocator on `stream`. The first query also
+ * allocates the gather's overflow bitmaps (n / 8 bytes per workgroup of its persistent grid,
+ * 768 workgroups on MI355X), which the index keeps, zero, until fpp_free_index; calls on
+ * different streams take turns on them (a call's stream waits for the previous call's work).
  * Errors: FPP_EINVAL, FPP_ENOMEM, FPP_EHIP, FPP_ESTATE (requested store not built).
  */
 int fpp_query(const fpp_index* index, const float* Q, int64_t m, int32_t k, int32_t qProbes,
@@ -163,7 +166,8 @@ int fpp_query_batch(const fpp_index* index, const float* Q, int64_t m, const int
                     const int32_t* qProbes, const fpp_query_opts* opts, int32_t* ids_out,
                     float* scores_out, void* stream);
 
-/* Bytes of scratch memory fpp_query_batch needs for m queries with the given maxima. */
+/* Bytes of scratch memory fpp_query_batch needs for m queries with the given maxima (besides
+   the overflow bitmaps the index keeps). */
 int64_t fpp_query_workspace_bytes(const fpp_index* index, int64_t m, int32_t k_max,
                                   int32_t qprobes_max, const fpp_query_opts* opts);
 

@@ -145,7 +145,14 @@ static void free_index_memory(fpp_index* ix) {
                   ix->center_vec, ix->Xsig};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (ix->gbm) (void)hipFree(ix->gbm);
+  if (ix->gbm_free) (void)hipEventDestroy(ix->gbm_free);
+  ix->gbm = nullptr;
+  ix->gbm_free = nullptr;
 }
+
+// Serialises the hand-over of an index's overflow bitmaps between calls (host side only).
+static std::mutex g_gbm_mu;
 
 // A scoped set of device buffers released on every exit path.
 struct DeviceScratch {
@@ -536,17 +543,33 @@ static int query_common(const fpp_index* ix, QuerySpec& qs, hipStream_t s) {
     qs.qp_max = qs.qp_uniform;
   }
   std::call_once(g_pool_once, configure_pool);
-  const Layout ly = plan_layout(ix, qs.m, qs.qp_max, qs.k_max, qs.store, qs.R_opt);
+  const Layout ly = plan_layout(ix, qs.m, qs.qp_max, qs.k_max, qs.store, qs.R_opt, (int64_t)4 << 30, false);
+  // the index's overflow bitmaps: this call's stream waits until the previous call is done with
+  // them; the lock is held while this call's kernels are enqueued
+  std::unique_lock<std::mutex> gbm_lock(g_gbm_mu);
+  if (!ix->gbm) {
+    const size_t b = overflow_bitmap_bytes(ix);
+    FPP_HIP(hipMalloc((void**)&ix->gbm, b));
+    const hipError_t e = hipMemset(ix->gbm, 0, b);
+    if (e == hipSuccess) {
+      const hipError_t f = hipEventCreateWithFlags(&ix->gbm_free, hipEventDisableTiming);
+      if (f != hipSuccess) ix->gbm_free = nullptr;
+    }
+    if (e != hipSuccess || !ix->gbm_free) {
+      (void)hipFree(ix->gbm);
+      ix->gbm = nullptr;
+      return hip_fail(e != hipSuccess ? e : hipErrorOutOfMemory, "overflow bitmaps", __FILE__, __LINE__);
+    }
+    FPP_HIP(hipEventRecord(ix->gbm_free, s));
+  }
+  FPP_HIP(hipStreamWaitEvent(s, ix->gbm_free, 0));
+  qs.gbm_ext = ix->gbm;
   size_t arr_bytes = 0;
   if (qs.k_host) arr_bytes = a256((size_t)qs.m * 16);
   unsigned char* ws = nullptr;
   FPP_HIP(hipMallocAsync((void**)&ws, ly.total + arr_bytes, s));
   int rc = FPP_OK;
   do {
-    if (ly.gbm) {
-      hipError_t e = hipMemsetAsync(ws + ly.off_gbm, 0, ly.total - ly.off_gbm, s);
-      if (e != hipSuccess) { rc = hip_fail(e, "hipMemsetAsync", __FILE__, __LINE__); break; }
-    }
     if (qs.k_host) {
       arrays = ws + ly.total;
       std::vector<int64_t> off((size_t)qs.m);
@@ -569,6 +592,11 @@ static int query_common(const fpp_index* ix, QuerySpec& qs, hipStream_t s) {
     }
     std::vector<hipEvent_t> ev;
     rc = run_queries(ix, qs, ly, ws, s, qs.stage_ms ? &ev : nullptr);
+    {
+      const hipError_t e = hipEventRecord(ix->gbm_free, s);
+      if (rc == FPP_OK && e != hipSuccess) rc = hip_fail(e, "hipEventRecord", __FILE__, __LINE__);
+    }
+    gbm_lock.unlock();
     if (qs.stage_ms) {
       for (int i = 0; i < 4; ++i) qs.stage_ms[i] = 0.0;
       if (rc == FPP_OK) {
@@ -695,7 +723,8 @@ int64_t fpp_query_workspace_bytes(const fpp_index* index, int64_t m, int32_t k_m
   if (!index || m < 0) return -1;
   const int32_t store = opts ? opts->store : FPP_STORE_FP32;
   const int32_t R = opts ? opts->rerank_R : 0;
-  const Layout ly = plan_layout(index, std::max<int64_t>(m, 1), qprobes_max, k_max, store, R);
+  const Layout ly = plan_layout(index, std::max<int64_t>(m, 1), qprobes_max, k_max, store, R,
+                                (int64_t)4 << 30, false);
   return (int64_t)(ly.total + a256((size_t)m * 16));
 }
 

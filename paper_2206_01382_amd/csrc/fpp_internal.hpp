@@ -72,6 +72,12 @@ struct fpp_index {
   uint32_t* offsets = nullptr;    // device [L][NB + 1], absolute positions into ids
   int32_t* ids = nullptr;         // device [total_ids]
 
+  // Overflow bitmaps of the gather kernel for fpp_query / fpp_query_ex / fpp_query_batch:
+  // allocated zeroed by the first query and kept zero by the kernel; calls take turns on them
+  // through gbm_free (each call's stream waits for the previous call's queries).
+  mutable uint32_t* gbm = nullptr;
+  mutable hipEvent_t gbm_free = nullptr;
+
   std::vector<int64_t> table_base;   // host [L + 1]
   int64_t total_ids = 0;
   int64_t max_bucket = 0;
