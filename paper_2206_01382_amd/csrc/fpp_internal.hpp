@@ -213,7 +213,7 @@ int check_store(const fpp_index* ix, int32_t store);
 // probes stay within `budget` bytes.
 Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max, int32_t store,
                    int32_t R_opt, int64_t budget = (int64_t)4 << 30, bool gbm_in_scratch = true);
-// Bytes of the overflow bitmaps of one score launch.
+// Bytes of the overflow bitmaps of one score launch and its work counters.
 size_t overflow_bitmap_bytes(const fpp_index* ix);
 // Runs hash -> probe selection -> score (-> rerank) over [0, qs.m) with device scratch `ws`
 // laid out by `ly`. Per-query arrays of qs must already be on the device.

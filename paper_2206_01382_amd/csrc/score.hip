@@ -317,6 +317,7 @@ struct ScoreParams {
   int32_t short_ld;
   int64_t* stats;
   uint32_t* gbitmap;         // [gridDim.x][bm_words], zero on entry and on exit
+  uint32_t* work;            // [2]: next query, finished workgroups; zero on entry and on exit
   int64_t bm_words;
   float sig_bits;            // SimHash: bits per signature
 };
@@ -327,6 +328,7 @@ struct SharedState {
   uint32_t uniq;
   uint32_t overflow;
   uint64_t thr;
+  int64_t qnext;       // the workgroup's current query
 };
 
 // LDS carve-up (byte offsets).
@@ -384,7 +386,13 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
   for (int i = tid; i < kSetSlots; i += kBlock) set[i] = kEmpty;
   __syncthreads();
 
-  for (int64_t q = blockIdx.x; q < p.m; q += gridDim.x) {
+  // queries are handed out one at a time from a device counter, so that workgroups that draw
+  // cheap queries take more of them and the launch ends evenly
+  for (;;) {
+    if (tid == 0) st->qnext = (int64_t)atomicAdd(&p.work[0], 1u);
+    __syncthreads();
+    const int64_t q = st->qnext;
+    if (q >= p.m) break;   // uniform
     const int k = p.k_arr ? p.k_arr[q] : p.k_uniform;
     const int kk = p.lowp ? short_len(p.R_opt, k) : k;   // list length kept by this pass
     float qv[C][EPC];
@@ -637,6 +645,15 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     }
     __syncthreads();
   }
+  // the last workgroup to finish returns the counters to zero for the next launch (every
+  // workgroup has drawn its last query before it counts itself finished)
+  if (tid == 0) {
+    __threadfence();
+    if (atomicAdd(&p.work[1], 1u) == gridDim.x - 1) {
+      atomicExch(&p.work[0], 0u);
+      atomicExch(&p.work[1], 0u);
+    }
+  }
 }
 
 // Exact float32 rerank of a short list (one 256-thread block per query); the same lane layout
@@ -746,6 +763,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.stats = a.stats;
   sp.gbitmap = a.gbitmap;
   sp.bm_words = overflow_bitmap_words(ix);
+  sp.work = a.gbitmap + (size_t)a.grid * (size_t)sp.bm_words;   // after the bitmaps
   sp.short_ids = a.short_ids;
   sp.short_ld = a.short_ld;
   sp.lowp = (a.store == FPP_STORE_FP32 || a.rerank_R < 0) ? 0 : 1;
