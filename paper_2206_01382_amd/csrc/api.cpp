@@ -391,7 +391,8 @@ int32_t short_list_len(int32_t R_opt, int32_t k) {
 size_t a256(size_t v) { return (v + 255) / 256 * 256; }
 
 size_t overflow_bitmap_bytes(const fpp_index* ix) {
-  // the bitmaps of the workgroups, then 256 bytes for the gather's work counters
+  // the bitmaps of the workgroups, then 256 bytes for the gather's work counters (words 0-1)
+  // and 16 bytes that stay zero (words 4-7)
   return (size_t)score_grid_blocks(ix) * (size_t)overflow_bitmap_words(ix) * 4 + 256;
 }
 

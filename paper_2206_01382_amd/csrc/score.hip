@@ -318,6 +318,7 @@ struct ScoreParams {
   int64_t* stats;
   uint32_t* gbitmap;         // [gridDim.x][bm_words], zero on entry and on exit
   uint32_t* work;            // [2]: next query, finished workgroups; zero on entry and on exit
+  const unsigned char* zero16;   // 16 bytes that stay zero (after the work counters)
   int64_t bm_words;
   float sig_bits;            // SimHash: bits per signature
 };
@@ -426,23 +427,31 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     // The block synchronises every PPC passes, when the candidate buffer may need compaction.
     // loads the pass's row chunks and, for the FP8 store, the per-row scale of the row this lane
     // reports after the reduction (issued with the rows, so its latency overlaps theirs)
+    // Every lane issues all its loads unconditionally, so that no load sits in a branch: the wait
+    // before a fold then covers exactly that pass's loads and lets the other pass's stay in
+    // flight. A row past the queue re-reads the queue's last row (its score is not used); a chunk
+    // past the row's end reads the 16 zero bytes at p.zero16. Requires rows > 0.
     auto load_pass = [&](uint32_t rbase, uint32_t rows, uint4 (&w)[U][C], float& scl) {
       if constexpr (STORE == FPP_STORE_FP8) {
         const uint32_t myrow = rbase + (uint32_t)reduced_row<G, U>(g) * RPI + sub;
-        scl = (myrow < rows && reports_row<G, U>(g)) ? p.scale[queue[myrow]] : 0.0f;
+        scl = p.scale[queue[myrow < rows ? myrow : rows - 1]];
+      }
+      uint32_t rid[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t row = rbase + u * RPI + sub;
+        rid[u] = queue[row < rows ? row : rows - 1];
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t row = rbase + u * RPI + sub;
-        const int32_t rid = row < rows ? (int32_t)queue[row] : -1;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
           const int ci = c * G + g;
-          if (rid >= 0 && ci < p.nchunks)
-            w[u][c] = *reinterpret_cast<const uint4*>(p.Xs + (size_t)rid * p.ld_bytes +
-                                                      (size_t)ci * 16);
-          else
-            w[u][c] = make_uint4(0u, 0u, 0u, 0u);
+          const unsigned char* a = ci < p.nchunks
+                                       ? p.Xs + (size_t)rid[u] * p.ld_bytes + (size_t)ci * 16
+                                       : p.zero16;
+          w[u][c] = *reinterpret_cast<const uint4*>(a);
         }
       }
     };
@@ -475,21 +484,19 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     // flush the queue through the scoring passes; `last` also leaves the candidates sorted
     auto score_queue = [&](bool last) {
       const uint32_t rows = st->qcount;
+      static_assert(PPC == 2, "two passes per barrier: set a folds while set b loads");
       for (uint32_t sb = 0; sb < rows || (last && sb == 0); sb += PPC * RPB) {
         const uint64_t thr = st->thr;
-        uint4 wa[U][C], wb[U][C];
-        float sa = 0.0f, sbs = 0.0f;
-        load_pass(sb + wave * RPW, rows, wa, sa);
-#pragma unroll 1
-        for (int ps = 0; ps < PPC; ps += 2) {
-          // even pass folds set a while set b loads; odd pass the other way round
-          const uint32_t b0 = sb + ps * RPB + wave * RPW, b1 = b0 + RPB;
-          if (ps + 1 < PPC) load_pass(b1, rows, wb, sbs);
-          if (b0 < rows) fold_pass(b0, rows, wa, sa, thr);     // wave-uniform: no sync inside
-          if (ps + 1 < PPC) {
-            if (ps + 2 < PPC) load_pass(b1 + RPB, rows, wa, sa);
-            if (b1 < rows) fold_pass(b1, rows, wb, sbs, thr);
-          }
+        // wave-uniform branches, no sync inside. Both passes' loads are issued before either
+        // fold (set b re-reads the queue's last row when its pass is past the queue).
+        const uint32_t b0 = sb + wave * RPW, b1 = b0 + RPB;
+        if (b0 < rows) {
+          uint4 wa[U][C], wb[U][C];
+          float sa = 0.0f, sbs = 0.0f;
+          load_pass(b0, rows, wa, sa);
+          load_pass(b1, rows, wb, sbs);
+          fold_pass(b0, rows, wa, sa, thr);
+          if (b1 < rows) fold_pass(b1, rows, wb, sbs, thr);
         }
         __syncthreads();
         const bool fin = last && sb + PPC * RPB >= rows;
@@ -764,6 +771,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.gbitmap = a.gbitmap;
   sp.bm_words = overflow_bitmap_words(ix);
   sp.work = a.gbitmap + (size_t)a.grid * (size_t)sp.bm_words;   // after the bitmaps
+  sp.zero16 = reinterpret_cast<const unsigned char*>(sp.work + 4);   // never written
   sp.short_ids = a.short_ids;
   sp.short_ld = a.short_ld;
   sp.lowp = (a.store == FPP_STORE_FP32 || a.rerank_R < 0) ? 0 : 1;
