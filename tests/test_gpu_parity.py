@@ -291,6 +291,30 @@ def test_query_many_candidates_uses_bitmap_dedup(qp):
     assert torch.equal(ids, ids2) and torch.equal(sc, sc2)
 
 
+def test_concurrent_queries_on_two_streams_share_the_bitmaps():
+    """Calls on two streams in flight at once (one spilling into the overflow bitmaps, one not)
+    each equal the same call made alone: the index's bitmaps and work counters are handed over
+    between the calls."""
+    w, oi, h, Xd, Qd = built("l2_clustered")
+    ref_a = F().fpp_query(h, Qd, 100, 2000)
+    ref_b = F().fpp_query(h, Qd.flip(0).contiguous(), 10, 24, store="bf16")
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    Qb = Qd.flip(0).contiguous()
+    torch.cuda.synchronize()
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(sa):
+            ra = F().fpp_query(h, Qd, 100, 2000, stream=sa)
+        with torch.cuda.stream(sb):
+            rb = F().fpp_query(h, Qb, 10, 24, store="bf16", stream=sb)
+        outs.append((ra, rb))
+    torch.cuda.synchronize()
+    for ra, rb in outs:
+        assert torch.equal(ra[0], ref_a[0]) and torch.equal(ra[1], ref_a[1])
+        assert torch.equal(rb[0], ref_b[0]) and torch.equal(rb[1], ref_b[1])
+
+
 def test_query_c1_published_qprobes():
     """The small workload as specified: k = 10, 4 probes per table (40 in total), and the
     literal total of 4."""
