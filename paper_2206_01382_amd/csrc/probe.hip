@@ -67,19 +67,38 @@ __device__ __forceinline__ float table_offset(const Lists& ls, int t, int l, boo
 
 // min(cap, #pairs of table t with score >= tau); A = list 2t (or t for l = 1), B = list 2t + 1.
 // The walk stops once `cap` pairs are counted, so its depth is bounded by cap.
+// #positions p < lim of list `list` whose score reaches tau: a + list[p] - off for a pair row
+// (a >= 0), list[p] - off alone for l = 1 (a < 0). The scores do not increase with p (the list is
+// sorted and float addition is monotone), so a binary search finds the boundary; the last LDS
+// position is tested first, so that a boundary inside the LDS prefix costs no device read.
+__device__ __forceinline__ int count_prefix(const Lists& ls, int list, float a, float tau, float off,
+                                            int lim) {
+  auto reaches = [&](int p) {
+    const float v = ls.get(list, p);
+    return (a < 0.0f ? v - off : pair_score(a, v, off)) >= tau;
+  };
+  int lo = 0, hi = lim;   // reaches(p) for p < lo, not for p >= hi
+  const int mp = ls.M < lim ? ls.M : lim;
+  if (mp > 0) {
+    if (reaches(mp - 1)) lo = mp;
+    else hi = mp - 1;
+  }
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (reaches(mid)) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ uint64_t count_table(const Lists& ls, int t, int l, float tau,
                                                 uint64_t cap, float off) {
   const int D = ls.D;
   const int lim = cap < (uint64_t)D ? (int)cap : D;
-  if (l == 1) {
-    int c = 0;
-    while (c < lim && ls.get(t, c) - off >= tau) ++c;
-    return (uint64_t)c;
-  }
+  if (l == 1) return (uint64_t)count_prefix(ls, t, -1.0f, tau, off, lim);
   const int la = 2 * t, lb = 2 * t + 1;
   const float a0 = ls.get(la, 0);
-  int j = 0;
-  while (j < lim && pair_score(a0, ls.get(lb, j), off) >= tau) ++j;
+  int j = count_prefix(ls, lb, a0, tau, off, lim);
   uint64_t c = 0;
   for (int i = 0; i < D && j > 0; ++i) {
     const float ai = ls.get(la, i);
@@ -501,13 +520,12 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     const uint16_t* C1 = Cq + (size_t)(2 * t) * D;
     const uint16_t* C2 = C1 + D;
     const int la_ = 2 * t, lb_ = 2 * t + 1;
-    int jg = 0, je = 0;
+    // row 0's counts, searched within the qP + 1 positions a selected pair can reach (a larger
+    // count changes no emission, since at most qP pairs are emitted)
+    const int lim_e = qP + 1 < (uint64_t)D ? (int)qP + 1 : D;
     const float a0 = ls.get(la_, 0);
-    while (jg < D && pair_score(a0, ls.get(lb_, jg), off) >= thr_gt) ++jg;
-    if (need) {
-      je = jg;
-      while (je < D && pair_score(a0, ls.get(lb_, je), off) >= tau_eq) ++je;
-    }
+    int jg = count_prefix(ls, lb_, a0, thr_gt, off, lim_e), je = 0;
+    if (need) je = count_prefix(ls, lb_, a0, tau_eq, off, lim_e);
     for (int i = 0; i < D && (jg > 0 || (je > 0 && te < need)); ++i) {
       const float ai = ls.get(la_, i);
       while (jg > 0 && !(pair_score(ai, ls.get(lb_, jg - 1), off) >= thr_gt)) --jg;
