@@ -373,12 +373,12 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   float* tops = pre + (size_t)l * L * (M + 1);             // [L] best pair of every table
   float* sel = tops + L;                                    // one value
   if (M % 4 == 0) {
-    // 16-byte loads, four per thread in flight before their LDS stores
+    // 16-byte loads, eight per thread in flight before their LDS stores
     const int per = M / 4, total4 = LF * per;
-    for (int b = tid; b < total4; b += 4 * kProbeThreads) {
-      float4 r[4];
+    for (int b = tid; b < total4; b += 8 * kProbeThreads) {
+      float4 r[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int i = b + u * kProbeThreads;
         if (i < total4) {
           const int list = i / per, e4 = i - list * per;
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
         }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const int i = b + u * kProbeThreads;
         if (i < total4) {
           const int list = i / per, e4 = i - list * per;
@@ -451,6 +451,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     for (int t = tid; t < L; t += kProbeThreads) {
       const float v = tops[t];
       int r = 0;
+#pragma unroll 4
       for (int u = 0; u < L; ++u) {
         const float w = tops[u];
         r += (w > v || (w == v && u < t)) ? 1 : 0;
