@@ -248,6 +248,21 @@ typedef struct fpp_server_stats {
 } fpp_server_stats;
 int fpp_server_get_stats(fpp_server* server, fpp_server_stats* stats);
 
+/*
+ * Open-loop load generator for measuring the server: request i (i < n_req) is submitted as
+ * fpp_server_submit would, at CLOCK_MONOTONIC time t0_ns + arrive_ns[i] (the call spins until
+ * then; late requests go at once), with queries Q[q_row[i] .. q_row[i] + m[i]) (Q device float32
+ * [*][d] of the index), k[i] and qProbes[i], and results at ids_out + out_off[i] and
+ * scores_out + out_off[i] (device, m[i] * k[i] values each). Host arrays of n_req entries;
+ * tickets[i] receives the ticket. Returns when the last request is submitted (not completed), or
+ * at the first failed submission with its error (tickets of the requests not submitted are 0).
+ * Latency of request i = completion time - (t0_ns + arrive_ns[i]), queueing included.
+ */
+int fpp_server_replay(fpp_server* server, const float* Q, int64_t n_req, int64_t t0_ns,
+                      const int64_t* arrive_ns, const int64_t* q_row, const int32_t* m,
+                      const int32_t* k, const int32_t* qProbes, int32_t* ids_out,
+                      float* scores_out, const int64_t* out_off, int64_t* tickets);
+
 /* Stop accepting work, finish what was admitted, join the loop thread and free it. */
 void fpp_server_destroy(fpp_server* server);
 

@@ -88,6 +88,7 @@ SIGNATURES = {
     "fpp_default_server_opts": (None, [ctypes.POINTER(fpp_server_opts)]),
     "fpp_server_create": (c_i32, [c_vp, ctypes.POINTER(fpp_server_opts), ctypes.POINTER(c_vp)]),
     "fpp_server_submit": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, ctypes.POINTER(c_i64)]),
+    "fpp_server_replay": (c_i32, [c_vp, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "fpp_server_poll": (c_i32, [c_vp, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "fpp_server_wait": (c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
                                 ctypes.POINTER(c_i64)]),
@@ -346,6 +347,24 @@ def fpp_server_submit(sv, q_ptr: int, m: int, k: int, qProbes: int, ids_ptr: int
     _check(lib().fpp_server_submit(sv, c_vp(q_ptr), m, k, qProbes, c_vp(ids_ptr), c_vp(scores_ptr),
                                    ctypes.byref(t)))
     return t.value
+
+
+def fpp_server_replay(sv, q_ptr: int, t0_ns: int, arrive_ns, q_row, m, k, qProbes, ids_ptr: int,
+                      scores_ptr: int, out_off):
+    """Submit request i at CLOCK_MONOTONIC t0_ns + arrive_ns[i] (open-loop load generator in
+    native code); returns the tickets. Host arrays: arrive_ns, q_row, out_off int64; m, k,
+    qProbes int32; offsets count elements of the device buffers at q_ptr / ids_ptr / scores_ptr."""
+    a = [np.ascontiguousarray(x, dtype=t) for x, t in ((arrive_ns, np.int64), (q_row, np.int64),
+                                                         (m, np.int32), (k, np.int32),
+                                                         (qProbes, np.int32), (out_off, np.int64))]
+    n = a[0].shape[0]
+    if any(x.shape != (n,) for x in a):
+        raise ValueError("request arrays must have the same length")
+    tickets = np.zeros(n, dtype=np.int64)
+    ptr = lambda x: x.ctypes.data_as(c_vp)
+    _check(lib().fpp_server_replay(sv, c_vp(q_ptr), n, t0_ns, ptr(a[0]), ptr(a[1]), ptr(a[2]), ptr(a[3]),
+                                   ptr(a[4]), c_vp(ids_ptr), c_vp(scores_ptr), ptr(a[5]), ptr(tickets)))
+    return tickets
 
 
 def fpp_server_poll(sv, ticket: int):

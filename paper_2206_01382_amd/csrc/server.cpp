@@ -460,6 +460,28 @@ int fpp_server_wait(fpp_server* sv, int64_t ticket, int64_t timeout_ms, int32_t*
   return FPP_OK;
 }
 
+int fpp_server_replay(fpp_server* sv, const float* Q, int64_t n_req, int64_t t0_ns,
+                      const int64_t* arrive_ns, const int64_t* q_row, const int32_t* m,
+                      const int32_t* k, const int32_t* qProbes, int32_t* ids_out,
+                      float* scores_out, const int64_t* out_off, int64_t* tickets) {
+  if (!sv || n_req < 0) return set_error("NULL server or n_req < 0"), FPP_EINVAL;
+  if (n_req == 0) return FPP_OK;
+  if (!Q || !arrive_ns || !q_row || !m || !k || !qProbes || !ids_out || !scores_out || !out_off ||
+      !tickets)
+    return set_error("NULL argument"), FPP_EINVAL;
+  for (int64_t i = 0; i < n_req; ++i) tickets[i] = 0;
+  const int64_t d = sv->ix->d;
+  for (int64_t i = 0; i < n_req; ++i) {
+    const int64_t t = t0_ns + arrive_ns[i];
+    while (now_ns() < t) {
+    }
+    const int rc = fpp_server_submit(sv, Q + q_row[i] * d, m[i], k[i], qProbes[i], ids_out + out_off[i],
+                                     scores_out + out_off[i], &tickets[i]);
+    if (rc != FPP_OK) return rc;
+  }
+  return FPP_OK;
+}
+
 int fpp_server_get_stats(fpp_server* sv, fpp_server_stats* out) {
   if (!sv || !out) return set_error("NULL argument"), FPP_EINVAL;
   std::lock_guard<std::mutex> g(sv->mu);

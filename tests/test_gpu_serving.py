@@ -159,3 +159,35 @@ def test_served_options_equal_direct_queries(env, store, probe_score):
     finally:
         if hh is not h:
             F.fpp_free_index(hh)
+
+
+def test_replay_submits_on_schedule_and_matches_direct_queries(env):
+    """The native load generator submits each request at its scheduled time; every result equals
+    the same query run alone, and no request is submitted before its time."""
+    F, h, Xd, Qd = env
+    rng = np.random.default_rng(5)
+    n = 80
+    m = rng.integers(1, 17, size=n).astype(np.int32)
+    k = rng.choice([1, 10], size=n).astype(np.int32)
+    qp = rng.choice([8, 40, 200], size=n).astype(np.int32)
+    q_row = np.array([int(rng.integers(0, Qd.shape[0] - 16)) for _ in range(n)], dtype=np.int64)
+    out_off = np.concatenate([[0], np.cumsum(m.astype(np.int64) * k)[:-1]]).astype(np.int64)
+    total = int((m.astype(np.int64) * k).sum())
+    ids = torch.full((total,), -7, dtype=torch.int32, device="cuda")
+    sc = torch.full((total,), 7.0, dtype=torch.float32, device="cuda")
+    arrive = np.cumsum(rng.exponential(100_000, size=n)).astype(np.int64)   # ~0.1 ms apart
+    sv = F.fpp_server_create(h, scratch_bytes=256 << 20, n_streams=2, max_batch=64)
+    try:
+        t0 = time.monotonic_ns() + 1_000_000
+        tickets = F.fpp_server_replay(sv, Qd.data_ptr(), t0, arrive, q_row, m, k, qp, ids.data_ptr(),
+                                      sc.data_ptr(), out_off)
+        stamps = [F.fpp_server_wait(sv, int(t), 60_000) for t in tickets.tolist()]
+    finally:
+        F.fpp_server_destroy(sv)
+    assert len(set(tickets.tolist())) == n and tickets.min() > 0
+    for i, (status, ts, td) in enumerate(stamps):
+        assert status == 0 and ts >= t0 + arrive[i] and td >= ts
+        r, mm, kk, o = int(q_row[i]), int(m[i]), int(k[i]), int(out_off[i])
+        ri, rs = F.fpp_query(h, Qd[r:r + mm].contiguous(), kk, int(qp[i]))
+        assert torch.equal(ids[o:o + mm * kk].view(mm, kk), ri)
+        assert torch.equal(sc[o:o + mm * kk].view(mm, kk), rs)
