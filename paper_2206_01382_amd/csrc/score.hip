@@ -1,8 +1,8 @@
 // Candidate gather, dedup, scoring and top-k on gfx950 (Section 3.4 multi-probe querying;
 // Section 1 problem statement: the answer is the top-k of x^T q).
 //
-// Persistent 256-thread workgroups (several per CU) walk queries q = blockIdx.x, + gridDim.x, ...
-// For each query:
+// Persistent 256-thread workgroups (three per CU) take queries one at a time from a device
+// counter. For each query:
 //   A. the probed CSR ranges are loaded 256 at a time and prefix-summed; every thread takes four
 //      consecutive entries, reads their ids and inserts them into an LDS open-addressing set
 //      (set semantics: an id is scored once however many buckets hold it). Past 3072 distinct
@@ -13,7 +13,8 @@
 //      and a fixed xor-shuffle tree over the G lanes finishes the sum. Scores therefore do not
 //      depend on batching or on which workgroup computes them.
 //   C. candidates above the running kk-th best key go to an LDS buffer that is sorted and cut to
-//      the best kk whenever it fills; the final sort gives (score desc, id asc) order.
+//      the best kk once it holds more than max(3 kk, 192); the final sort gives (score desc,
+//      id asc) order.
 // Keys are 64-bit: order-preserving float bits << 32 | (0xffffffff - id).
 // The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
 // scores exactly in float32 from the FP32 store.
