@@ -215,14 +215,86 @@ __device__ __forceinline__ bool out_of_order(const uint64_t (&key)[E], int j0, i
   return bad;
 }
 
-// VEC: rows of V are 16-byte aligned and d % 4 == 0. FULL: D == P (every output is listed), which
-// turns the per-element bounds tests into constants. Only the first W entries of each sorted list
-// are stored (rounded up to the E entries of a lane; W = D stores all).
-template <int P, bool VEC, bool FULL>
+// Sorts an item's first D 32-bit keys (lane li holds positions li * E .. + E), turns them into
+// exact 64-bit keys (values from the item's LDS copy yl, by index), repairs and, if needed,
+// re-sorts them, and stores the first W entries of the list at ola / olc.
+template <int SP, int E, int LPI>
+__device__ __forceinline__ void sort_and_store(uint32_t (&k32)[E], int li, int D, const float* yl,
+                                               uint64_t* slot, bool valid, int W, float* ola,
+                                               uint16_t* olc) {
+  const int j0 = li * E;
+  const uint32_t imask = (uint32_t)D - 1u;
+  sort32_desc<SP, E, LPI>(k32, li, j0, D);
+  wave_lds_sync();
+  uint64_t key[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (j0 + e < D) {
+      const int i = (int)(imask - (k32[e] & imask));
+      key[e] = exact_key(yl[i], i);
+    } else {
+      key[e] = 0ull;
+    }
+  }
+  repair_runs<E, LPI>(key, j0, D);
+  if (__ballot(out_of_order<E, LPI>(key, j0, D)) != 0ull) {
+    // wave-uniform: every y has been read before the slots are overwritten
+    wave_lds_sync();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < D) slot[j0 + e] = key[e];
+    wave_lds_sync();
+    lds_sort64_desc<E>(slot, j0, D);
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (j0 + e < D) key[e] = slot[j0 + e];
+  }
+  if (!valid || j0 >= W) return;
+  uint32_t av[E], cv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const uint64_t kk = key[e];
+    const int idx = 0xffff - (int)(((uint32_t)kk & 0x1ffffu) >> 1);
+    av[e] = (uint32_t)(kk >> 32);
+    cv[e] = (uint32_t)((kk & 1u) ? idx + D : idx);
+  }
+  if constexpr (E % 8 == 0) {
+    if (j0 + E <= D) {
+      // D >= E is a power of two: the lane's 4E + 2E bytes are 16-byte aligned
+#pragma unroll
+      for (int g4 = 0; g4 < E / 4; ++g4)
+        *reinterpret_cast<uint4*>(ola + j0 + 4 * g4) =
+            make_uint4(av[4 * g4], av[4 * g4 + 1], av[4 * g4 + 2], av[4 * g4 + 3]);
+#pragma unroll
+      for (int g8 = 0; g8 < E / 8; ++g8) {
+        const uint32_t* c = cv + 8 * g8;
+        *reinterpret_cast<uint4*>(olc + j0 + 8 * g8) =
+            make_uint4(c[0] | (c[1] << 16), c[2] | (c[3] << 16), c[4] | (c[5] << 16), c[6] | (c[7] << 16));
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int p = j0 + e;
+    if (p < D) {
+      ola[p] = __uint_as_float(av[e]);
+      olc[p] = (uint16_t)cv[e];
+    }
+  }
+}
+
+constexpr int kAnyD = 0;   // D <= P, checked per element
+constexpr int kFull = 1;   // D == P: every output is listed, the bounds tests are constants
+constexpr int kHalf = 2;   // D == P / 2: the listed outputs are redistributed over all lanes
+
+// VEC: rows of V are 16-byte aligned and d % 4 == 0. MODE: kAnyD, kFull or kHalf. Only the first W
+// entries of each sorted list are stored (rounded up to a lane's entries; W = D stores all).
+template <int P, bool VEC, int MODE>
 __global__ __launch_bounds__(256) void hash_query_kernel(
     const float* __restrict__ V, uint32_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
     int LF, int D_arg, int W, float* __restrict__ la, uint16_t* __restrict__ lc) {
-  const int D = FULL ? P : D_arg;
+  const int D = MODE == kFull ? P : (MODE == kHalf ? P / 2 : D_arg);
   constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI, IPW = QLayout<P>::IPW;
   const int lane = threadIdx.x & 63;
   const int li = lane % LPI;
@@ -332,65 +404,23 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
       k32[e] = 0u;
     }
   }
-  sort32_desc<P, E, LPI>(k32, li, j0, D);
-  wave_lds_sync();
-  uint64_t key[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    if (j0 + e < D) {
-      const int i = (int)(imask - (k32[e] & imask));
-      key[e] = exact_key(yl[i], i);
-    } else {
-      key[e] = 0ull;
-    }
-  }
-  repair_runs<E, LPI>(key, j0, D);
-  if (__ballot(out_of_order<E, LPI>(key, j0, D)) != 0ull) {
-    // wave-uniform: every y has been read before the slots are overwritten
-    wave_lds_sync();
+  float* ola = la + (size_t)it * D;
+  uint16_t* olc = lc + (size_t)it * D;
+  if constexpr (MODE == kHalf) {
+    // D = P / 2: only the lower half of the item's lanes hold listed outputs. Their keys move
+    // through the second half of the LDS slot so that every lane sorts E / 2 of them.
+    constexpr int E2 = E / 2;
+    uint32_t* kl = reinterpret_cast<uint32_t*>(slot) + D;
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (j0 + e < D) slot[j0 + e] = key[e];
+      if (j0 + e < D) kl[j0 + e] = k32[e];
     wave_lds_sync();
-    lds_sort64_desc<E>(slot, j0, D);
+    uint32_t k2[E2];
 #pragma unroll
-    for (int e = 0; e < E; ++e)
-      if (j0 + e < D) key[e] = slot[j0 + e];
-  }
-  if (!valid || j0 >= W) return;
-  float* ola = la + (size_t)item * D;
-  uint16_t* olc = lc + (size_t)item * D;
-  uint32_t av[E], cv[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const uint64_t kk = key[e];
-    const int idx = 0xffff - (int)(((uint32_t)kk & 0x1ffffu) >> 1);
-    av[e] = (uint32_t)(kk >> 32);
-    cv[e] = (uint32_t)((kk & 1u) ? idx + D : idx);
-  }
-  if constexpr (E % 8 == 0) {
-    if (j0 + E <= D) {
-      // D >= E is a power of two: the lane's 4E + 2E bytes are 16-byte aligned
-#pragma unroll
-      for (int g4 = 0; g4 < E / 4; ++g4)
-        *reinterpret_cast<uint4*>(ola + j0 + 4 * g4) =
-            make_uint4(av[4 * g4], av[4 * g4 + 1], av[4 * g4 + 2], av[4 * g4 + 3]);
-#pragma unroll
-      for (int g8 = 0; g8 < E / 8; ++g8) {
-        const uint32_t* c = cv + 8 * g8;
-        *reinterpret_cast<uint4*>(olc + j0 + 8 * g8) =
-            make_uint4(c[0] | (c[1] << 16), c[2] | (c[3] << 16), c[4] | (c[5] << 16), c[6] | (c[7] << 16));
-      }
-      return;
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int p = j0 + e;
-    if (p < D) {
-      ola[p] = __uint_as_float(av[e]);
-      olc[p] = (uint16_t)cv[e];
-    }
+    for (int e = 0; e < E2; ++e) k2[e] = kl[li * E2 + e];
+    sort_and_store<P / 2, E2, LPI>(k2, li, D, yl, slot, valid, W, ola, olc);
+  } else {
+    sort_and_store<P, E, LPI>(k32, li, D, yl, slot, valid, W, ola, olc);
   }
 }
 
@@ -452,18 +482,24 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
   const int64_t items = m * LF;
   if (items >= (int64_t)1 << 31) return hipErrorInvalidValue;   // callers chunk the queries
   const bool vec = (ix->d % 4 == 0) && (ldv % 4 == 0) && ((uintptr_t)V % 16 == 0);
-  const bool full = ix->D == ix->P;
-#define FPP_HQ_LAUNCH(PP, VV, FF)                                                              \
-  hipLaunchKernelGGL((hash_query_kernel<PP, VV, FF>), grid, dim3(256), lds, s, V, (uint32_t)m,   \
+  const bool full = ix->D == ix->P, half = 2 * ix->D == ix->P;
+#define FPP_HQ_LAUNCH(PP, VV, MM)                                                              \
+  hipLaunchKernelGGL((hash_query_kernel<PP, VV, MM>), grid, dim3(256), lds, s, V, (uint32_t)m,   \
                      ldv, ix->d, ix->sign_mask, LF, ix->D, W, la, lc)
 #define FPP_HQ(PP)                                                                             \
   case PP: {                                                                                   \
     const int64_t waves = (items + QLayout<PP>::IPW - 1) / QLayout<PP>::IPW;                   \
     const dim3 grid((unsigned)((waves + 3) / 4));                                              \
     const size_t lds = (size_t)4 * QLayout<PP>::IPW * ix->D * sizeof(uint64_t);               \
-    if (vec && full) FPP_HQ_LAUNCH(PP, true, true);                                            \
-    else if (vec) FPP_HQ_LAUNCH(PP, true, false);                                              \
-    else FPP_HQ_LAUNCH(PP, false, false);                                                      \
+    if (vec && full) {                                                                         \
+      FPP_HQ_LAUNCH(PP, true, kFull);                                                          \
+    } else if (vec && half && PP >= 32) {                                                      \
+      if constexpr (PP >= 32) FPP_HQ_LAUNCH(PP, true, kHalf);                                  \
+    } else if (vec) {                                                                          \
+      FPP_HQ_LAUNCH(PP, true, kAnyD);                                                          \
+    } else {                                                                                   \
+      FPP_HQ_LAUNCH(PP, false, kAnyD);                                                         \
+    }                                                                                          \
     break;                                                                                     \
   }
   switch (ix->P) {
