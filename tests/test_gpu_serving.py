@@ -182,6 +182,11 @@ def test_replay_submits_on_schedule_and_matches_direct_queries(env):
         tickets = F.fpp_server_replay(sv, Qd.data_ptr(), t0, arrive, q_row, m, k, qp, ids.data_ptr(),
                                       sc.data_ptr(), out_off)
         stamps = [F.fpp_server_wait(sv, int(t), 60_000) for t in tickets.tolist()]
+        # a request the server rejects (more queries than one launch packs) stops the replay there
+        with pytest.raises(F.FppError) as e:
+            F.fpp_server_replay(sv, Qd.data_ptr(), time.monotonic_ns(), [0, 0], [0, 0], [65, 1], [1, 1],
+                                [8, 8], ids.data_ptr(), sc.data_ptr(), [0, 0])
+        assert e.value.code == F.FPP_ECAPACITY
     finally:
         F.fpp_server_destroy(sv)
     assert len(set(tickets.tolist())) == n and tickets.min() > 0
