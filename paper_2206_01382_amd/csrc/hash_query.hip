@@ -44,8 +44,9 @@ struct QLayout {
 };
 
 // v + (v of lane ^ X) * mul. For X = 1, 2 and 8 the partner is a DPP operand of one v_fmac (quad
-// permutes, and a rotation by 8 within a 16-lane row); the s_nop gives the two wait states a DPP
-// read needs after a VALU write of its source. Other distances go through xor_lanes.
+// permutes, and a rotation by 8 within a 16-lane row), for X = 4 after one DPP move; the s_nop
+// gives the two wait states a DPP read needs after a VALU write of its source. Other distances go
+// through xor_lanes.
 template <int X>
 __device__ __forceinline__ float fmac_xor(float v, float mul) {
   float src = v;
@@ -55,6 +56,10 @@ __device__ __forceinline__ float fmac_xor(float v, float mul) {
     asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
   } else if constexpr (X == 8) {
     asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:8 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
+  } else if constexpr (X == 4) {
+    // x ^ 4 = (x ^ 7) ^ 3: a half-row mirror move, then the quad reversal as the DPP operand
+    src = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));
+    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[3,2,1,0] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
   } else {
     v = __builtin_fmaf(xor_lanes<X>(v), mul, v);
   }
@@ -91,55 +96,65 @@ __device__ __forceinline__ void ce_desc(uint64_t& a, uint64_t& b) {
 }
 
 // Bitonic sort (descending) of the first D keys (D a power of two <= P) in the item layout: lane
-// li holds elements j0 + e, j0 = li * E. Stages k < E have compile-time directions; from k = E
-// on the direction is uniform over a lane, so lanes of ascending blocks complement their keys
-// (which reverses the order) and every compare-exchange keeps the larger value in front.
-template <int P, int E, int LPI>
-__device__ __forceinline__ void sort32_desc(uint32_t (&key)[E], int li, int j0, int D) {
-  uint32_t flipm = 0u;
+// li holds elements j0 + e, j0 = li * E. Every merge of two sorted blocks of k / 2 starts by
+// comparing position p with its mirror image p ^ (k - 1) inside the block, which leaves two
+// bitonic halves, every key of the first at least every key of the second; half-cleaners at
+// distances k / 4, ..., 1 then sort them. All compare-exchanges keep the larger key in front, so
+// no block runs in the other direction. Inside a lane the pairs are registers; across lanes the
+// partner comes from one lane exchange, and the median of (key, partner, 0 or ~0) keeps the larger
+// in the lower lane of the pair and the smaller in the upper one.
+template <int E, int J>
+__device__ __forceinline__ void half_clean(uint32_t (&key)[E], int li) {
+  if constexpr (J > 0) {
+    if constexpr (J < E) {
 #pragma unroll
-  for (int k = 2; k <= P; k <<= 1) {
-    if (k <= D) {
-      if (k < E) {
+      for (int e = 0; e < E; ++e)
+        if ((e & J) == 0) ce_desc(key[e], key[e | J]);
+    } else {
+      const uint32_t lim = (li & (J / E)) == 0 ? 0xffffffffu : 0u;
 #pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-          for (int e = 0; e < E; ++e) {
-            if ((e & j) == 0) {
-              if ((e & k) == 0) ce_desc(key[e], key[e | j]);
-              else ce_desc(key[e | j], key[e]);
-            }
-          }
-        }
-      } else {
-        const uint32_t want = (j0 & k) == 0 ? 0u : 0xffffffffu;
-        const uint32_t x = want ^ flipm;
-#pragma unroll
-        for (int e = 0; e < E; ++e) key[e] ^= x;
-        flipm = want;
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-          if (j < E) {
-#pragma unroll
-            for (int e = 0; e < E; ++e)
-              if ((e & j) == 0) ce_desc(key[e], key[e | j]);
-          } else {
-            // median of (key, partner, 0 or ~0): the larger in the lower lane, the smaller above
-            const uint32_t lim = (li & (j / E)) == 0 ? 0xffffffffu : 0u;
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-              const uint32_t o = xor_lanes_n(key[e], j / E);
-              const uint32_t mx = key[e] > o ? key[e] : o, mn = key[e] > o ? o : key[e];
-              const uint32_t c = mx < lim ? mx : lim;
-              key[e] = mn > c ? mn : c;
-            }
-          }
-        }
+      for (int e = 0; e < E; ++e) {
+        const uint32_t o = xor_lanes<J / E>(key[e]);
+        const uint32_t mx = key[e] > o ? key[e] : o, mn = key[e] > o ? o : key[e];
+        const uint32_t c = mx < lim ? mx : lim;
+        key[e] = mn > c ? mn : c;
       }
     }
+    half_clean<E, J / 2>(key, li);
   }
+}
+
+template <int P, int E, int K>
+__device__ __forceinline__ void sort_levels(uint32_t (&key)[E], int li, int D) {
+  if constexpr (K <= P) {
+    if (K > D) return;
+    if constexpr (K <= E) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) key[e] ^= flipm;
+      for (int e = 0; e < E; ++e)
+        if ((e & (K >> 1)) == 0) ce_desc(key[e], key[e ^ (K - 1)]);
+    } else {
+      // position li * E + e pairs with (li ^ (K / E - 1)) * E + (E - 1 - e)
+      const uint32_t lim = (li & (K / (2 * E))) == 0 ? 0xffffffffu : 0u;
+#pragma unroll
+      for (int e = 0; e < E / 2; ++e) {
+        const uint32_t a = key[e], b = key[E - 1 - e];
+        const uint32_t pa = mirror_lanes<K / E - 1>(b), pb = mirror_lanes<K / E - 1>(a);
+        const uint32_t mxa = a > pa ? a : pa, mna = a > pa ? pa : a;
+        const uint32_t mxb = b > pb ? b : pb, mnb = b > pb ? pb : b;
+        const uint32_t ca = mxa < lim ? mxa : lim, cb = mxb < lim ? mxb : lim;
+        key[e] = mna > ca ? mna : ca;
+        key[E - 1 - e] = mnb > cb ? mnb : cb;
+      }
+    }
+    half_clean<E, K / 4>(key, li);
+    sort_levels<P, E, K * 2>(key, li, D);
+  }
+}
+
+template <int P, int E, int LPI>
+__device__ __forceinline__ void sort32_desc(uint32_t (&key)[E], int li, int j0, int D) {
+  (void)j0;
+  sort_levels<P, E, 2>(key, li, D);
 }
 
 __device__ __forceinline__ void wave_lds_sync() {

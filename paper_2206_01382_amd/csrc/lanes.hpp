@@ -50,6 +50,27 @@ __device__ __forceinline__ uint64_t xor_lanes(uint64_t v) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Lane x receives the value of lane x ^ M for M = 2^a - 1 (the mirror image inside aligned
+// groups of M + 1 lanes): one DPP move up to M = 15 (quad reversal, half-row and row mirror),
+// then the row swaps for the bits 16 and 32.
+template <int M>
+__device__ __forceinline__ uint32_t mirror_lanes(uint32_t v) {
+  static_assert(M == 1 || M == 3 || M == 7 || M == 15 || M == 31 || M == 63, "mirror width");
+  const int s = (int)v;
+  if constexpr (M == 1) {
+    return xor_lanes<1>(v);
+  } else if constexpr (M == 3) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x1B, 0xF, 0xF, true);   // quad_perm 3,2,1,0
+  } else if constexpr (M == 7) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x141, 0xF, 0xF, true);  // row_half_mirror
+  } else {
+    const uint32_t r = (uint32_t)__builtin_amdgcn_mov_dpp(s, 0x140, 0xF, 0xF, true);  // row_mirror
+    if constexpr (M == 15) return r;
+    else if constexpr (M == 31) return xor_lanes<16>(r);
+    else return xor_lanes<32>(xor_lanes<16>(r));
+  }
+}
+
 // Run-time distance (a compile-time constant after unrolling); distances >= 64 are invalid.
 template <typename T>
 __device__ __forceinline__ T xor_lanes_n(T v, int x) {
