@@ -279,6 +279,12 @@ int fpp_debug_signs(const fpp_index* index, int8_t* signs_out);
 int fpp_debug_query_lists(const fpp_index* index, const float* V, int64_t m, float* abs_out,
                           int32_t* code_out, void* stream);
 
+/* As fpp_debug_query_lists, but the hash kernel stores only what the query path stores for a
+ * probe selection that reads the first W entries of every list (1 <= W <= D, else FPP_EINVAL):
+ * positions [0, W) of each list are defined, later positions are unspecified. */
+int fpp_debug_query_list_prefix(const fpp_index* index, const float* V, int64_t m, int32_t W,
+                                float* abs_out, int32_t* code_out, void* stream);
+
 /* Build-side records of table t: for every point p and r < iProbes, the bucket and key of its
  * r-th best pair (device uint32 bucket_out / float32 key_out, [n][iProbes]). */
 int fpp_debug_build_records(const fpp_index* index, int32_t t, uint32_t* bucket_out,

@@ -96,6 +96,7 @@ SIGNATURES = {
     "fpp_server_destroy": (None, [c_vp]),
     "fpp_debug_signs": (c_i32, [c_vp, c_vp]),
     "fpp_debug_query_lists": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "fpp_debug_query_list_prefix": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_vp, c_vp, c_vp]),
     "fpp_debug_build_records": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "fpp_debug_export_table": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "fpp_debug_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp]),
@@ -259,14 +260,20 @@ def fpp_debug_signs(h) -> np.ndarray:
     return out
 
 
-def fpp_debug_query_lists(h, V, stream=None):
+def fpp_debug_query_lists(h, V, stream=None, W=None):
+    """Sorted query hash lists [m][L][l][D]; with W, only positions [0, W) are defined."""
     torch = _torch()
     inf = fpp_index_get_info(h)
     m = V.shape[0]
     a = torch.empty((m, inf["L"], inf["l"], inf["D"]), dtype=torch.float32, device=V.device)
     c = torch.empty((m, inf["L"], inf["l"], inf["D"]), dtype=torch.int32, device=V.device)
-    _check(lib().fpp_debug_query_lists(h, _dev(V, torch.float32, "V"), m, c_vp(a.data_ptr()),
-                                       c_vp(c.data_ptr()), _stream(stream)))
+    Vp = _dev(V, torch.float32, "V")
+    if W is None:
+        _check(lib().fpp_debug_query_lists(h, Vp, m, c_vp(a.data_ptr()), c_vp(c.data_ptr()),
+                                           _stream(stream)))
+    else:
+        _check(lib().fpp_debug_query_list_prefix(h, Vp, m, int(W), c_vp(a.data_ptr()),
+                                                 c_vp(c.data_ptr()), _stream(stream)))
     return a, c
 
 

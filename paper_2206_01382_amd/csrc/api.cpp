@@ -770,14 +770,22 @@ int fpp_debug_signs(const fpp_index* ix, int8_t* out) {
 
 int fpp_debug_query_lists(const fpp_index* ix, const float* V, int64_t m, float* abs_out,
                           int32_t* code_out, void* stream) {
+  if (!ix) return set_error("NULL argument"), FPP_EINVAL;
+  return fpp_debug_query_list_prefix(ix, V, m, ix->D, abs_out, code_out, stream);
+}
+
+int fpp_debug_query_list_prefix(const fpp_index* ix, const float* V, int64_t m, int32_t W,
+                                float* abs_out, int32_t* code_out, void* stream) {
   if (!ix || (m > 0 && (!V || !abs_out || !code_out))) return set_error("NULL argument"), FPP_EINVAL;
+  if (W < 1 || W > ix->D) return set_error("prefix %d outside [1, D = %d]", W, ix->D), FPP_EINVAL;
   if (m <= 0) return FPP_OK;
   hipStream_t s = (hipStream_t)stream;
   const size_t cnt = (size_t)m * ix->L * ix->l * ix->D;
   DeviceScratch sc;
   uint16_t* lc = nullptr;
   FPP_TRY(sc.get(&lc, cnt));
-  FPP_HIP(launch_hash_query(ix, V, m, ix->d, abs_out, lc, ix->D, s));
+  FPP_HIP(hipMemsetAsync(lc, 0, cnt * 2, s));
+  FPP_HIP(launch_hash_query(ix, V, m, ix->d, abs_out, lc, W, s));
   std::vector<uint16_t> h(cnt);
   FPP_HIP(hipMemcpyAsync(h.data(), lc, cnt * 2, hipMemcpyDeviceToHost, s));
   FPP_HIP(hipStreamSynchronize(s));

@@ -261,39 +261,39 @@ __device__ __forceinline__ bool out_of_order(const uint64_t (&key)[E], int j0, i
   return bad;
 }
 
-// Sorts an item's first D 32-bit keys (lane li holds positions li * E .. + E), turns them into
-// exact 64-bit keys (values from the item's LDS copy yl, by index), repairs and, if needed,
-// re-sorts them, and stores the first W entries of the list at ola / olc.
-template <int SP, int E, int LPI>
-__device__ __forceinline__ void sort_and_store(uint32_t (&k32)[E], int li, int D, const float* yl,
-                                               uint64_t* slot, bool valid, int W, float* ola,
-                                               uint16_t* olc) {
+// Turns an item's first Dn sorted 32-bit keys (lane li holds positions li * E .. + E; Dn <= D, the
+// keys' index bits and the codes refer to the D outputs) into exact 64-bit keys (values from the
+// item's LDS copy yl, by index), repairs and, if needed, re-sorts them, and stores the first W
+// entries of the list at ola / olc.
+template <int E, int LPI>
+__device__ __forceinline__ void finish_list(const uint32_t (&k32)[E], int li, int Dn, int D,
+                                            const float* yl, uint64_t* slot, bool valid, int W,
+                                            float* ola, uint16_t* olc) {
   const int j0 = li * E;
   const uint32_t imask = (uint32_t)D - 1u;
-  sort32_desc<SP, E, LPI>(k32, li, j0, D);
   wave_lds_sync();
   uint64_t key[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    if (j0 + e < D) {
+    if (j0 + e < Dn) {
       const int i = (int)(imask - (k32[e] & imask));
       key[e] = exact_key(yl[i], i);
     } else {
       key[e] = 0ull;
     }
   }
-  repair_runs<E, LPI>(key, j0, D);
-  if (__ballot(out_of_order<E, LPI>(key, j0, D)) != 0ull) {
+  repair_runs<E, LPI>(key, j0, Dn);
+  if (__ballot(out_of_order<E, LPI>(key, j0, Dn)) != 0ull) {
     // wave-uniform: every y has been read before the slots are overwritten
     wave_lds_sync();
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (j0 + e < D) slot[j0 + e] = key[e];
+      if (j0 + e < Dn) slot[j0 + e] = key[e];
     wave_lds_sync();
-    lds_sort64_desc<E>(slot, j0, D);
+    lds_sort64_desc<E>(slot, j0, Dn);
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (j0 + e < D) key[e] = slot[j0 + e];
+      if (j0 + e < Dn) key[e] = slot[j0 + e];
   }
   if (!valid || j0 >= W) return;
   uint32_t av[E], cv[E];
@@ -305,8 +305,8 @@ __device__ __forceinline__ void sort_and_store(uint32_t (&k32)[E], int li, int D
     cv[e] = (uint32_t)((kk & 1u) ? idx + D : idx);
   }
   if constexpr (E % 8 == 0) {
-    if (j0 + E <= D) {
-      // D >= E is a power of two: the lane's 4E + 2E bytes are 16-byte aligned
+    if (j0 + E <= Dn) {
+      // Dn >= E is a power of two: the lane's 4E + 2E bytes are 16-byte aligned
 #pragma unroll
       for (int g4 = 0; g4 < E / 4; ++g4)
         *reinterpret_cast<uint4*>(ola + j0 + 4 * g4) =
@@ -323,11 +323,55 @@ __device__ __forceinline__ void sort_and_store(uint32_t (&k32)[E], int li, int D
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int p = j0 + e;
-    if (p < D) {
+    if (p < Dn) {
       ola[p] = __uint_as_float(av[e]);
       olc[p] = (uint16_t)cv[e];
     }
   }
+}
+
+// Sorts an item's first D 32-bit keys (D <= SP; lane li holds positions li * E .. + E) and
+// finishes the list. When at most D / 2 entries are stored and all SP positions are listed
+// (D == SP), only the first D / 2 sorted keys are finished, spread over all lanes (E / 2 each,
+// through the second half of the LDS slot): the 32-bit order is exact up to runs of equal
+// truncated |y|, so when no run crosses position D / 2 those keys are exactly the D / 2 best
+// entries. A wavefront where some list has such a run finishes all D keys.
+template <int SP, int E, int LPI>
+__device__ __forceinline__ void sort_and_store(uint32_t (&k32)[E], int li, int D, const float* yl,
+                                               uint64_t* slot, bool valid, int W, float* ola,
+                                               uint16_t* olc) {
+  const int j0 = li * E;
+  sort32_desc<SP, E, LPI>(k32, li, j0, D);
+  if constexpr (E >= 2 && E % 2 == 0) {
+    if (D == SP && 2 * W <= D) {   // uniform
+      constexpr int C = SP / 2;
+      constexpr uint32_t imask = (uint32_t)SP - 1u;
+      bool cross;   // positions C - 1 and C hold equal truncated |y|
+      if constexpr (C % E == 0) {
+        // the last key of lane C / E - 1 and the first of the next lane
+        const uint32_t nxt0 =
+            (uint32_t)__builtin_amdgcn_update_dpp(0, (int)k32[0], 0x130, 0xF, 0xF, false);   // wave_shl:1
+        cross = li == C / E - 1 && (k32[E - 1] ^ nxt0) <= imask;
+      } else {
+        cross = li == C / E && (k32[C % E - 1] ^ k32[C % E]) <= imask;
+      }
+      if (__ballot(cross) == 0ull) {
+        constexpr int E2 = E / 2;
+        uint32_t* kl = reinterpret_cast<uint32_t*>(slot) + D;
+        wave_lds_sync();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+          if (j0 + e < C) kl[j0 + e] = k32[e];
+        wave_lds_sync();
+        uint32_t k2[E2];
+#pragma unroll
+        for (int e = 0; e < E2; ++e) k2[e] = kl[li * E2 + e];
+        finish_list<E2, LPI>(k2, li, C, D, yl, slot, valid, W, ola, olc);
+        return;
+      }
+    }
+  }
+  finish_list<E, LPI>(k32, li, D, D, yl, slot, valid, W, ola, olc);
 }
 
 constexpr int kAnyD = 0;   // D <= P, checked per element

@@ -209,6 +209,45 @@ def test_query_hash_lists_d128_D128_bit_exact():
         F().fpp_free_index(h)
 
 
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64", "pad_d100_D16"])
+def test_query_hash_list_prefix_bit_exact(name):
+    """With W <= D / 2 stored entries the kernel finishes only the first D / 2 sorted keys (all
+    D when an equal-key run crosses position D / 2): positions [0, W) are bit-exact on random and
+    near-tie vectors, for W around that cut."""
+    w, oi, h, Xd, Qd = built(name)
+    D = w["D"]
+    V = np.concatenate([w["Q"][:40], _near_tie_vectors(w["X"].shape[1], np.random.default_rng(7))])
+    ref = {(t, f): O.hash_lists(V, oi.signs[t, f], D) for t in range(w["L"]) for f in range(w["l"])}
+    for W in sorted({1, max(1, D // 4), max(1, D // 2 - 1), D // 2, D // 2 + 1, D}):
+        a, c = F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda(), W=W)
+        a, c = a.cpu().numpy(), c.cpu().numpy()
+        for (t, f), hl in ref.items():
+            np.testing.assert_array_equal(a[:, t, f, :W].view(np.uint32), hl.a[:, :W].view(np.uint32))
+            np.testing.assert_array_equal(c[:, t, f, :W], hl.code[:, :W])
+
+
+def test_query_hash_list_prefix_d128_D128_bit_exact():
+    """The headline shape with the headline prefix (qProbes = 50 reads 52 entries) and the
+    prefixes around D / 2 = 64, on random vectors and on vectors with runs of equal keys."""
+    X, Q = synthdata.clustered_sphere(2_000, 128, 200, 20, 0.3, seed=22)
+    Xd = torch.from_numpy(X).cuda()
+    h = F().fpp_build_index(Xd, 4, 128, 0.3, 3, 98, l=2)
+    try:
+        V = np.concatenate([Q, _near_tie_vectors(128, np.random.default_rng(8))])
+        S = O.rotation_signs(98, 4, 2, 128)
+        ref = {(t, f): O.hash_lists(V, S[t, f], 128) for t in range(4) for f in range(2)}
+        for W in (1, 52, 63, 64, 65):
+            a, c = F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda(), W=W)
+            a, c = a.cpu().numpy(), c.cpu().numpy()
+            for (t, f), hl in ref.items():
+                np.testing.assert_array_equal(a[:, t, f, :W].view(np.uint32), hl.a[:, :W].view(np.uint32))
+                np.testing.assert_array_equal(c[:, t, f, :W], hl.code[:, :W])
+        with pytest.raises(F().FppError):
+            F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda(), W=129)
+    finally:
+        F().fpp_free_index(h)
+
+
 @pytest.mark.parametrize("name", list(CONFIGS))
 def test_build_records_bit_exact(name):
     w, oi, h, Xd, Qd = built(name)
