@@ -466,10 +466,26 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   // and equals qP only when no table was capped, so every decision below is the uncapped one.
   const uint64_t cap = qP + 1;
   uint32_t lo = ord_of(mn), hi = ord_of(mx) + 1u;   // cnt(lo) >= qP > cnt(hi), in key order
-  uint64_t c_hi = 0;
-  bool exact = false;
+  // The next key comes from the secant through (lo, c_lo) and (hi, c_hi) once c_lo is known,
+  // kept at least 1/16 of the bracket from either end; a secant step that does not halve the
+  // bracket is followed by a bisection step, so the search takes at most twice the bisection's
+  // steps. Any key inside the bracket keeps the invariant, so the result does not depend on
+  // these choices.
+  uint64_t c_hi = 0, c_lo = 0;
+  bool exact = false, bisect = true;
   while (hi - lo > 1u) {
-    const uint32_t mid = lo + (hi - lo) / 2u;
+    const uint32_t span = hi - lo;
+    uint32_t mid = lo + span / 2u;
+    const bool secant = !bisect && c_lo > qP;
+    if (secant) {
+      const float f = (float)(c_lo - qP) / (float)(c_lo - c_hi);
+      const uint32_t g = span / 16u > 1u ? span / 16u : 1u;
+      const float o = f * (float)span;
+      uint32_t off = o < (float)g ? g : (o > (float)(span - g) ? span - g : (uint32_t)o);
+      if (off < 1u) off = 1u;
+      if (off > span - 1u) off = span - 1u;
+      mid = lo + off;
+    }
     const float tau = of_ord(mid);
     uint64_t c = 0;
     for (int t = tid; t < L; t += kProbeThreads) c += count_table(ls, t, l, tau, cap, table_offset(ls, t, l, gap));
@@ -481,10 +497,12 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     }
     if (c > qP) {
       lo = mid;
+      c_lo = c;
     } else {
       hi = mid;
       c_hi = c;
     }
+    bisect = secant && hi - lo > span / 2u;
   }
   const float thr_gt = of_ord(exact ? lo : hi);
   const float tau_eq = of_ord(lo);
