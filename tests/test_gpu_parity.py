@@ -54,6 +54,9 @@ CONFIGS = {
                           centers=10, spread=0.4),
     "l1_L24_D16": dict(kind="cl", n=2_000, d=16, L=24, D=16, l=1, alpha=0.5, iProbes=2, m=20,
                        centers=8, spread=0.5),
+    # d not a multiple of 4: element loads in the hash kernels, ragged row chunks in the gather
+    "odd_d30_D32": dict(kind="cl", n=2_500, d=30, L=3, D=32, l=2, alpha=0.4, iProbes=2, m=20,
+                        centers=8, spread=0.4),
 }
 SEED = 1234
 
@@ -209,7 +212,8 @@ def test_query_hash_lists_d128_D128_bit_exact():
         F().fpp_free_index(h)
 
 
-@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64", "pad_d100_D16"])
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64", "pad_d100_D16",
+                                  "odd_d30_D32"])
 def test_query_hash_list_prefix_bit_exact(name):
     """With W <= D / 2 stored entries the kernel finishes only the first D / 2 sorted keys (all
     D when an equal-key run crosses position D / 2): positions [0, W) are bit-exact on random and
