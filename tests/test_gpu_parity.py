@@ -252,6 +252,28 @@ def test_query_hash_list_prefix_d128_D128_bit_exact():
         F().fpp_free_index(h)
 
 
+@pytest.mark.parametrize("P,l", [(2, 1), (2, 2), (4, 2), (8, 1), (8, 2)])
+def test_query_hash_lists_tiny_P_bit_exact(P, l):
+    """Rotations of 2 to 8 elements (one lane per item): whole lists and every prefix length."""
+    rng = np.random.default_rng(P * 10 + l)
+    X = rng.standard_normal((300, P)).astype(np.float32)
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    h = F().fpp_build_index(torch.from_numpy(X).cuda(), 3, P, 0.5, 1, 97, l=l)
+    try:
+        V = np.concatenate([X[:30], _near_tie_vectors(P, np.random.default_rng(9))])
+        S = O.rotation_signs(97, 3, l, P)
+        ref = {(t, f): O.hash_lists(V, S[t, f], P) for t in range(3) for f in range(l)}
+        for W in [None] + list(range(1, P + 1)):
+            a, c = F().fpp_debug_query_lists(h, torch.from_numpy(V).cuda(), W=W)
+            a, c = a.cpu().numpy(), c.cpu().numpy()
+            n = P if W is None else W
+            for (t, f), hl in ref.items():
+                np.testing.assert_array_equal(a[:, t, f, :n].view(np.uint32), hl.a[:, :n].view(np.uint32))
+                np.testing.assert_array_equal(c[:, t, f, :n], hl.code[:, :n])
+    finally:
+        F().fpp_free_index(h)
+
+
 @pytest.mark.parametrize("name", list(CONFIGS))
 def test_build_records_bit_exact(name):
     w, oi, h, Xd, Qd = built(name)
