@@ -95,14 +95,6 @@ __device__ __forceinline__ void ce_desc(uint64_t& a, uint64_t& b) {
   b = y;
 }
 
-// Bitonic sort (descending) of the first D keys (D a power of two <= P) in the item layout: lane
-// li holds elements j0 + e, j0 = li * E. Every merge of two sorted blocks of k / 2 starts by
-// comparing position p with its mirror image p ^ (k - 1) inside the block, which leaves two
-// bitonic halves, every key of the first at least every key of the second; half-cleaners at
-// distances k / 4, ..., 1 then sort them. All compare-exchanges keep the larger key in front, so
-// no block runs in the other direction. Inside a lane the pairs are registers; across lanes the
-// partner comes from one lane exchange, and the median of (key, partner, 0 or ~0) keeps the larger
-// in the lower lane of the pair and the smaller in the upper one.
 // Batcher's odd-even merge sort of n keys: comparator number c (in the network's order) as
 // lo * 1024 + hi, or -1 past the last one; all comparators keep the larger key at lo. 63
 // comparators for n = 16 and 19 for n = 8, against 80 and 24 for the bitonic network.
@@ -128,6 +120,13 @@ __device__ __forceinline__ void lane_sort_desc(uint32_t (&key)[E]) {
   }
 }
 
+// Bitonic merges (descending) in the item layout: lane li holds positions li * E + e. Every merge
+// of two sorted blocks of k / 2 starts by comparing position p with its mirror image p ^ (k - 1)
+// inside the block, which leaves two bitonic halves, every key of the first at least every key
+// of the second; half-cleaners at distances k / 4, ..., 1 then sort them. All compare-exchanges
+// keep the larger key in front, so no block runs in the other direction. Inside a lane the pairs
+// are registers; across lanes the partner comes from one lane exchange, and the median of (key,
+// partner, 0 or ~0) keeps the larger in the lower lane of the pair and the smaller in the upper.
 template <int E, int J>
 __device__ __forceinline__ void half_clean(uint32_t (&key)[E], int li) {
   if constexpr (J > 0) {
@@ -176,6 +175,8 @@ __device__ __forceinline__ void sort_levels(uint32_t (&key)[E], int li, int D) {
   }
 }
 
+// Sorts the first D keys (D a power of two <= P) descending: each lane's E keys with the odd-even
+// network when D >= E, then the bitonic merges across lanes (for D < E, bitonic merges only).
 template <int P, int E, int LPI>
 __device__ __forceinline__ void sort32_desc(uint32_t (&key)[E], int li, int j0, int D) {
   (void)j0;
