@@ -294,7 +294,8 @@ __device__ __forceinline__ uint32_t set_hash(uint32_t id) {
 
 struct ScoreParams {
   const unsigned char* Xs;   // store base
-  int64_t ld_bytes;          // store row stride in bytes
+  uint32_t ld_bytes;         // store row stride in bytes (at most 4 KB: the offset of a row is
+                             // one 32 x 32 -> 64-bit multiply-add)
   int nchunks;               // 16-byte chunks per stored row
   const float* scale;        // FP8 per-row scales
   const uint32_t* offsets;
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         for (int c = 0; c < C; ++c) {
           const int ci = c * G + g;
           const unsigned char* a = ci < p.nchunks
-                                       ? p.Xs + (size_t)rid[u] * p.ld_bytes + (size_t)ci * 16
+                                       ? p.Xs + (uint64_t)rid[u] * p.ld_bytes + (uint32_t)ci * 16u
                                        : p.zero16;
           w[u][c] = *reinterpret_cast<const uint4*>(a);
         }
@@ -782,17 +783,17 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   switch (a.store) {
     case FPP_STORE_FP32:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->X);
-      sp.ld_bytes = (int64_t)ix->ldx * 4;
+      sp.ld_bytes = (uint32_t)ix->ldx * 4u;
       sp.nchunks = ix->ldx / 4;
       return dispatch_store<FPP_STORE_FP32>(sp, grid, s);
     case FPP_STORE_BF16:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xbf16);
-      sp.ld_bytes = (int64_t)ix->ld16 * 2;
+      sp.ld_bytes = (uint32_t)ix->ld16 * 2u;
       sp.nchunks = ix->ld16 / 8;
       return dispatch_store<FPP_STORE_BF16>(sp, grid, s);
     case FPP_STORE_FP8:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xfp8);
-      sp.ld_bytes = (int64_t)ix->ld8;
+      sp.ld_bytes = (uint32_t)ix->ld8;
       sp.nchunks = ix->ld8 / 16;
       sp.scale = ix->fp8_scale;
       return dispatch_store<FPP_STORE_FP8>(sp, grid, s);
@@ -800,7 +801,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
       // the query rows (a.Q, a.ldq) are signature words; F * D <= 1024 bits: 8 chunks at most
       if (ix->ldsig > 32) return hipErrorInvalidValue;
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xsig);
-      sp.ld_bytes = (int64_t)ix->ldsig * 4;
+      sp.ld_bytes = (uint32_t)ix->ldsig * 4u;
       sp.nchunks = ix->ldsig / 4;
       sp.d = ix->ldsig;
       sp.sig_bits = (float)(ix->sigF * ix->D);
