@@ -278,18 +278,24 @@ class Index:
     threshold: np.float32 | None = None            # bound on |y| of a threshold-filter build
 
 
-def build_table(X, signs_t, D, l, alpha, iProbes, rounding="ceil", kappa=0, threshold=None):
+def build_table(X, signs_t, D, l, alpha, iProbes, rounding="ceil", kappa=0, threshold=None,
+                chunk=1 << 17):
     """One hash table: hash, top-iProbes buckets per point, per-bucket filter, CSR.
 
     threshold (float32 bound on |y|): the global-threshold filter keeps a record when each of
     its l projections is >= the bound, and every bucket keeps all such records.
+    Points are hashed `chunk` rows at a time (each row's hash depends on that row alone), which
+    bounds the memory of the sorted lists.
     """
     n = X.shape[0]
-    lists = [hash_lists(X, signs_t[f], D) for f in range(l)]
-    if threshold is None:
-        bucket, key = top_pairs(lists, D, iProbes)
-    else:
-        bucket, key, parts = top_pairs(lists, D, iProbes, with_parts=True)
+    pieces = []
+    for r0 in range(0, n, chunk):
+        lists = [hash_lists(X[r0:r0 + chunk], signs_t[f], D) for f in range(l)]
+        pieces.append(top_pairs(lists, D, iProbes, with_parts=threshold is not None))
+    bucket = np.concatenate([p[0] for p in pieces])
+    key = np.concatenate([p[1] for p in pieces])
+    if threshold is not None:
+        parts = tuple(np.concatenate([p[2][f] for p in pieces]) for f in range(l))
     K = bucket.shape[1]
     rb = bucket.reshape(-1)
     rk = key.reshape(-1)
@@ -574,10 +580,7 @@ def query_reranked(index: Index, Q: np.ndarray, k: int, qProbes: int, R: int, st
     Q = np.atleast_2d(np.asarray(Q, dtype=np.float32))
     if storage == "simhash":
         F = simhash_functions
-        store = simhash_bits(index.X, index.signs, index.D, F) if store is None else store
         qsig = simhash_bits(Q, index.signs, index.D, F)
-    elif store is None:
-        store = dequantized_store(index.X, storage)
     m = Q.shape[0]
     ids = np.empty((m, k), dtype=np.int64)
     sc = np.empty((m, k), dtype=np.float64)
@@ -585,10 +588,18 @@ def query_reranked(index: Index, Q: np.ndarray, k: int, qProbes: int, R: int, st
     for i in range(m):
         pl = probes(index, Q[i], qProbes)
         cand = candidates(index, pl)
-        if storage == "simhash":
-            approx = simhash_score(store[cand], qsig[i])
+        # the store's rows of the candidates (every quantiser works row by row, so quantising
+        # only these rows gives the values of the whole store)
+        if store is not None:
+            rows = store[cand]
+        elif storage == "simhash":
+            rows = simhash_bits(index.X[cand], index.signs, index.D, F)
         else:
-            approx = store[cand] @ Q[i].astype(np.float64)
+            rows = dequantized_store(index.X[cand], storage)
+        if storage == "simhash":
+            approx = simhash_score(rows, qsig[i])
+        else:
+            approx = rows @ Q[i].astype(np.float64)
         sl, _ = topk_order(approx, cand, R)
         short[i] = sl
         sl = sl[sl >= 0]

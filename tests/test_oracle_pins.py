@@ -27,6 +27,59 @@ def test_splitmix64_published_outputs():
     assert got == vals
 
 
+def _splitmix64_stepped(seed, count):
+    """The published generator as a stateful stream (splitmix64.c, next()): advance the state by
+    the golden-ratio increment, then mix; a loop over Python integers, independent of the
+    oracle's closed form for output c."""
+    mask = (1 << 64) - 1
+    state = seed & mask
+    out = []
+    for _ in range(count):
+        state = (state + 0x9E3779B97F4A7C15) & mask
+        z = state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def test_rotation_signs_are_bit63_of_the_published_stream():
+    """Reading R9: sign -1 exactly when bit 63 of the output is set. The five published outputs
+    at seed 1234567 give + + - + - (two of them are >= 2^63)."""
+    vals = [int(l) for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt"))
+            if l.strip() and not l.startswith("#")]
+    want = [-1 if v >> 63 else 1 for v in vals]
+    assert want == [1, 1, -1, 1, -1]
+    S = O.rotation_signs(1234567, 1, 1, 5)
+    assert S[0, 0, 0].tolist() == want
+
+
+def test_rotation_signs_counter_layout_hand_computed():
+    """Reading R9's counter ((t*l + f)*3 + r)*P + j, at L = 3, l = 2, P = 4, for elements whose
+    counters are worked out by hand here: (t, f, r, j) = (1, 0, 2, 3) -> ((2 + 0)*3 + 2)*4 + 3
+    = 35; (1, 1, 1, 2) -> ((2 + 1)*3 + 1)*4 + 2 = 42; (2, 1, 0, 1) -> ((4 + 1)*3 + 0)*4 + 1 = 61;
+    (0, 1, 2, 0) -> ((0 + 1)*3 + 2)*4 + 0 = 20. The expected signs come from the stepped
+    generator. The seed is chosen so that the plausible wrong layouts (r and j swapped in rank,
+    table and function swapped, round outermost) give a different sign on at least one element."""
+    seed = 20220601
+    stream = _splitmix64_stepped(seed, 3 * 2 * 3 * 4)
+    sign = [-1 if v >> 63 else 1 for v in stream]
+    S = O.rotation_signs(seed, 3, 2, 4)
+    cases = {(1, 0, 2, 3): 35, (1, 1, 1, 2): 42, (2, 1, 0, 1): 61, (0, 1, 2, 0): 20}
+    for (t, f, r, j), c in cases.items():
+        assert S[t, f, r, j] == sign[c], (t, f, r, j)
+    # the same elements under wrong layouts read other counters with other signs
+    wrong = [
+        lambda t, f, r, j: ((t * 2 + f) * 4 + j) * 3 + r,       # j before r
+        lambda t, f, r, j: ((f * 3 + t) * 3 + r) * 4 + j,       # function-major
+        lambda t, f, r, j: ((r * 3 + t) * 2 + f) * 4 + j,       # round-major
+    ]
+    for w in wrong:
+        assert any(sign[w(*e)] != sign[c] for e, c in cases.items())
+    # and every element follows the stepped stream
+    np.testing.assert_array_equal(S.reshape(-1), np.array(sign, dtype=np.int8))
+
+
 def test_signs_balanced_and_seeded():
     S = O.rotation_signs(7, 4, 2, 256)
     assert S.shape == (4, 2, 3, 256)
@@ -588,3 +641,54 @@ def test_rerank_with_full_short_list_equals_plain_query(storage):
     ri, rs, short = O.query_reranked(idx, Q, 10, qProbes=30, R=400, storage=storage)
     np.testing.assert_array_equal(pi, ri)
     np.testing.assert_array_equal(ps, rs)
+
+
+def test_chunked_hashing_gives_the_same_table():
+    """build_table hashes rows in chunks; every row's hash depends on that row alone, so a chunk of
+    7 rows and one chunk of all rows give identical tables."""
+    X = _uniform_data(300, 20, 81)
+    S = O.rotation_signs(3, 1, 2, 32)
+    a = O.build_table(X, S[0], 16, 2, 0.4, 3)
+    b = O.build_table(X, S[0], 16, 2, 0.4, 3, chunk=7)
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_rerank_short_list_cut_by_approximate_score(storage):
+    """With R < |C| the short list is the first R candidates by (approximate score desc, id asc)
+    and the answer is the exact top-k of that list. Checked against a Python enumeration that
+    takes the dequantised values from torch's own casts (a library routine) and sums products
+    with math.fsum; the data makes the approximate and the exact top-R differ, so ordering the
+    short list by the exact score, or ascending, fails."""
+    torch = pytest.importorskip("torch")
+    # tight clusters: neighbours' scores differ by less than the quantisation error
+    rng = np.random.default_rng(91)
+    base = _uniform_data(4, 24, 92).astype(np.float64)
+    X = base[rng.integers(0, 4, size=600)] + 0.004 * rng.standard_normal((600, 24))
+    X = (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+    Q = base[np.arange(12) % 4] + 0.004 * rng.standard_normal((12, 24))
+    Q = (Q / np.linalg.norm(Q, axis=1, keepdims=True)).astype(np.float32)
+    idx = O.build_index(X, L=4, D=8, alpha=0.6, iProbes=2, seed=5, l=2)
+    R, k = 6, 3
+    ids, sc, short = O.query_reranked(idx, Q, k, qProbes=40, R=R, storage=storage)
+    if storage == "bf16":
+        deq = torch.from_numpy(X).to(torch.bfloat16).to(torch.float64).numpy()
+    else:
+        s = (np.max(np.abs(X), axis=1) / np.float32(448.0)).astype(np.float32)
+        codes = torch.from_numpy((X / s[:, None]).astype(np.float32)).to(torch.float8_e4m3fn)
+        deq = codes.to(torch.float64).numpy() * s.astype(np.float64)[:, None]
+    differs = 0
+    for r in range(Q.shape[0]):
+        cand = O.candidates(idx, O.probes(idx, Q[r], 40))
+        assert len(cand) > R
+        q = [float(v) for v in Q[r]]
+        approx = {int(c): math.fsum(float(deq[c, j]) * q[j] for j in range(24)) for c in cand}
+        exact = {int(c): math.fsum(float(X[c, j]) * q[j] for j in range(24)) for c in cand}
+        want = sorted(approx, key=lambda c: (-approx[c], c))[:R]
+        assert short[r].tolist() == want, r
+        top = sorted(want, key=lambda c: (-exact[c], c))[:k]
+        assert ids[r].tolist() == top
+        np.testing.assert_allclose(sc[r], [exact[c] for c in top], rtol=1e-15, atol=1e-15)
+        differs += set(want) != set(sorted(exact, key=lambda c: (-exact[c], c))[:R])
+    assert differs > 0
