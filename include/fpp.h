@@ -263,6 +263,12 @@ int fpp_server_replay(fpp_server* server, const float* Q, int64_t n_req, int64_t
                       const int32_t* k, const int32_t* qProbes, int32_t* ids_out,
                       float* scores_out, const int64_t* out_off, int64_t* tickets);
 
+/* For tests of failure handling: the next n batches the loop launches fail after their first
+ * kernel is on the stream, as a failing HIP call would leave them. Each such batch's requests
+ * complete with status FPP_EHIP, its scratch returns to the pool, and the loop goes on admitting
+ * and serving later requests. n = 0 cancels. Errors: FPP_EINVAL. */
+int fpp_server_debug_fail_batches(fpp_server* server, int32_t n);
+
 /* Stop accepting work, finish what was admitted, join the loop thread and free it. */
 void fpp_server_destroy(fpp_server* server);
 

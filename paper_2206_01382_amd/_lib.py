@@ -93,6 +93,7 @@ SIGNATURES = {
     "fpp_server_wait": (c_i32, [c_vp, c_i64, c_i64, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
                                 ctypes.POINTER(c_i64)]),
     "fpp_server_get_stats": (c_i32, [c_vp, ctypes.POINTER(fpp_server_stats)]),
+    "fpp_server_debug_fail_batches": (c_i32, [c_vp, c_i32]),
     "fpp_server_destroy": (None, [c_vp]),
     "fpp_debug_signs": (c_i32, [c_vp, c_vp]),
     "fpp_debug_query_lists": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, c_vp]),
@@ -390,6 +391,11 @@ def fpp_server_get_stats(sv) -> dict:
     s = fpp_server_stats()
     _check(lib().fpp_server_get_stats(sv, ctypes.byref(s)))
     return {name: getattr(s, name) for name, _ in fpp_server_stats._fields_}
+
+
+def fpp_server_debug_fail_batches(sv, n: int):
+    """The next n batches fail after their first kernel (failure-handling tests)."""
+    _check(lib().fpp_server_debug_fail_batches(sv, n))
 
 
 def fpp_server_destroy(sv):

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -23,6 +24,7 @@
 #include <time.h>
 
 #include "fpp_internal.hpp"
+#include "server_pool.hpp"
 
 namespace fpp {
 namespace {
@@ -72,59 +74,6 @@ struct Request {
   int32_t status = 1;   // 1 pending, 0 done, < 0 error
 };
 
-// First-fit allocator over one device buffer.
-class Pool {
- public:
-  void init(size_t bytes) {
-    cap_ = bytes;
-    free_.clear();
-    free_[0] = bytes;
-  }
-  bool alloc(size_t bytes, size_t* off) {
-    bytes = a256(bytes);
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        *off = it->first;
-        const size_t rem = it->second - bytes, start = it->first + bytes;
-        free_.erase(it);
-        if (rem) free_[start] = rem;
-        used_ += bytes;
-        high_ = std::max(high_, used_);
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t bytes) {
-    bytes = a256(bytes);
-    used_ -= bytes;
-    auto it = free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-  size_t largest_free() const {
-    size_t b = 0;
-    for (auto& kv : free_) b = std::max(b, kv.second);
-    return b;
-  }
-  size_t capacity() const { return cap_; }
-  size_t high_water() const { return high_; }
-
- private:
-  std::map<size_t, size_t> free_;
-  size_t cap_ = 0, used_ = 0, high_ = 0;
-};
-
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
@@ -163,6 +112,7 @@ struct fpp_server {
   std::thread loop;
   fpp_server_stats stats{};
   int device = 0;
+  std::atomic<int32_t> fail_batches{0};   // batches still to fail on request (tests)
 };
 
 namespace fpp {
@@ -211,6 +161,14 @@ int launch_batch(fpp_server* sv, Slot& s) {
   FPP_HIP(hipMemcpyAsync(s.d_kq, s.h_kq, sizeof(int32_t) * 2 * m, hipMemcpyHostToDevice, st));
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)m), dim3(256), 0, st, s.d_desc, m, ix->d, s.d_Q);
   FPP_HIP(hipGetLastError());
+  {
+    // a failure requested by fpp_server_debug_fail_batches, at the point where a failing HIP call
+    // would leave the batch: part of its work is already on the stream
+    int32_t f = sv->fail_batches.load();
+    while (f > 0 && !sv->fail_batches.compare_exchange_weak(f, f - 1)) {
+    }
+    if (f > 0) return set_error("batch failed on request"), FPP_EHIP;
+  }
   QuerySpec qs;
   qs.Q = s.d_Q;
   qs.m = m;
@@ -263,33 +221,18 @@ void server_loop(fpp_server* sv) {
     // 2. admit FIFO while a slot and scratch are free
     for (auto& s : sv->slots) {
       if (s.busy || sv->queue.empty()) continue;
-      int64_t m = 0;
-      int32_t kmax = 0, qpmax = 0;
-      size_t need = 0;
-      std::vector<std::shared_ptr<Request>> take;
-      while (!sv->queue.empty()) {
-        auto& r = sv->queue.front();
-        const int64_t m2 = m + r->m;
-        if (m2 > sv->opts.max_batch && m > 0) break;
-        const int32_t k2 = std::max(kmax, r->k), q2 = std::max(qpmax, r->qp);
-        const size_t need2 = batch_bytes(sv->ix, sv->opts, m2, k2, q2);
-        if (need2 > sv->pool.largest_free()) break;
-        m = m2;
-        kmax = k2;
-        qpmax = q2;
-        need = need2;
-        take.push_back(r);
-        sv->queue.pop_front();
-      }
-      if (take.empty()) break;   // the head waits for scratch
-      size_t off = 0;
-      sv->pool.alloc(need, &off);
-      s.ws_off = off;
-      s.ws_bytes = need;
-      s.reqs = std::move(take);
+      const Admitted a = admit_fifo(
+          sv->queue.begin(), sv->queue.end(), sv->opts.max_batch, sv->pool,
+          [](const std::shared_ptr<Request>& r) { return AdmitShape{r->m, r->k, r->qp}; },
+          [sv](int64_t m, int32_t k, int32_t qp) { return batch_bytes(sv->ix, sv->opts, m, k, qp); });
+      if (a.taken == 0) break;   // the head waits for scratch
+      s.reqs.assign(sv->queue.begin(), sv->queue.begin() + (std::ptrdiff_t)a.taken);
+      sv->queue.erase(sv->queue.begin(), sv->queue.begin() + (std::ptrdiff_t)a.taken);
+      s.ws_off = a.offset;
+      s.ws_bytes = a.bytes;
       s.busy = true;
       ++sv->stats.batches;
-      sv->stats.queries += m;
+      sv->stats.queries += a.m;
       lk.unlock();
       const int rc = launch_batch(sv, s);
       lk.lock();
@@ -479,6 +422,12 @@ int fpp_server_replay(fpp_server* sv, const float* Q, int64_t n_req, int64_t t0_
                                      scores_out + out_off[i], &tickets[i]);
     if (rc != FPP_OK) return rc;
   }
+  return FPP_OK;
+}
+
+int fpp_server_debug_fail_batches(fpp_server* sv, int32_t n) {
+  if (!sv || n < 0) return set_error("NULL server or n < 0"), FPP_EINVAL;
+  sv->fail_batches.store(n);
   return FPP_OK;
 }
 
