@@ -157,6 +157,25 @@ int fpp_query_ex(const fpp_index* index, const float* Q, int64_t m, int32_t k, i
                  const fpp_query_opts* opts, int32_t* ids_out, float* scores_out, void* stream);
 
 /*
+ * fpp_query_ex for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same results as fpp_query_ex with the same
+ * arguments, but no call to hipMalloc, hipMallocAsync, hipFree or any allocating routine. Every
+ * per-call buffer lives in one static device array of 128 MiB, which each device that loads the
+ * library holds until the process ends: the gather's overflow dedup bitmaps (n / 8 bytes per
+ * workgroup; the gather runs on as many workgroups, at most its usual grid, as have a bitmap
+ * within 32 MiB) and the lists, probes and short lists of one chunk of queries (any m is taken
+ * in chunks that fit). A fill kernel on `stream` clears the bitmaps and work counters at the
+ * start of each call. All calls on one device share the array: calls whose work overlaps on a
+ * device (other threads, other streams) race and must be serialised by the caller.
+ * opts->stage_ms must be NULL. Errors: as fpp_query_ex, FPP_EINVAL for stage_ms, and
+ * FPP_ECAPACITY when one overflow bitmap exceeds 32 MiB (n > 268,435,455) or one query's
+ * scratch does not fit beside the bitmaps.
+ */
+int fpp_query_ex_noalloc(const fpp_index* index, const float* Q, int64_t m, int32_t k,
+                         int32_t qProbes, const fpp_query_opts* opts, int32_t* ids_out,
+                         float* scores_out, void* stream);
+
+/*
  * Mixed batch in one launch sequence: query i uses k[i] and qProbes[i] (host arrays of m
  * entries, same ranges as above) and writes its k[i] results at ids_out + off_i and
  * scores_out + off_i with off_i = k[0] + ... + k[i-1] (packed). Other arguments as fpp_query_ex.

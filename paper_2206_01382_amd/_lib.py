@@ -79,6 +79,7 @@ SIGNATURES = {
     "fpp_default_query_opts": (None, [ctypes.POINTER(fpp_query_opts)]),
     "fpp_query": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp, c_vp]),
     "fpp_query_ex": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(fpp_query_opts), c_vp, c_vp, c_vp]),
+    "fpp_query_ex_noalloc": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(fpp_query_opts), c_vp, c_vp, c_vp]),
     "fpp_query_batch": (c_i32, [c_vp, c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(fpp_query_opts), c_vp, c_vp, c_vp]),
     "fpp_query_workspace_bytes": (c_i64, [c_vp, c_i64, c_i32, c_i32, ctypes.POINTER(fpp_query_opts)]),
     "fpp_index_get_info": (c_i32, [c_vp, ctypes.POINTER(fpp_index_info)]),
@@ -202,6 +203,24 @@ def fpp_query(h, Q, k: int, qProbes: int, *, store: str = "fp32", rerank_R: int 
     _check(lib().fpp_query_ex(h, qp, m, k, qProbes, ctypes.byref(o),
                               c_vp(ids.data_ptr()) if m else c_vp(0), c_vp(sc.data_ptr()) if m else c_vp(0),
                               _stream(stream)))
+    return (ids, sc, st) if stats else (ids, sc)
+
+
+def fpp_query_ex_noalloc(h, Q, k: int, qProbes: int, *, store: str = "fp32", rerank_R: int = 0,
+                         stats: bool = False, stream=None, probe_score: str = "sum"):
+    """fpp_query without allocation inside the library (static device scratch; overlapping calls
+    on one device race). The output tensors are allocated here, by the caller of the C ABI."""
+    torch = _torch()
+    m = Q.shape[0]
+    qp = _dev(Q, torch.float32, "Q") if m else c_vp(0)
+    ids = torch.empty((m, k), dtype=torch.int32, device=Q.device)
+    sc = torch.empty((m, k), dtype=torch.float32, device=Q.device)
+    st = torch.empty((m, 3), dtype=torch.int64, device=Q.device) if stats else None
+    o = fpp_query_opts(STORES[store], rerank_R, c_vp(st.data_ptr()) if stats and m else None, None,
+                       PROBE_SCORES[probe_score])
+    _check(lib().fpp_query_ex_noalloc(h, qp, m, k, qProbes, ctypes.byref(o),
+                                      c_vp(ids.data_ptr()) if m else c_vp(0),
+                                      c_vp(sc.data_ptr()) if m else c_vp(0), _stream(stream)))
     return (ids, sc, st) if stats else (ids, sc)
 
 
