@@ -26,91 +26,70 @@ __device__ __forceinline__ float flip(float v, uint32_t mask) {
 // lane; stages with h >= E exchange with lane g ^ (h / E).
 //
 // After the rotation of one function the group keeps the KMAX best (|y|, index) entries in
-// (|y| desc, index asc) order together with their codes. For l = 2 the candidate pairs are the
-// list positions (i, j) with (i + 1)(j + 1) <= K: any other pair is preceded by at least K
-// pairs of its row or column, because float addition is monotone and ties go to the smaller
-// position. Records of a point are written at the slot given by the pair's rank.
+// (|y| desc, index asc) order, as 64-bit list keys that also carry the codes. For l = 2 the
+// candidate pairs are the list positions (i, j) with (i + 1)(j + 1) <= K: any other pair is
+// preceded by at least K pairs of its row or column, because float addition is monotone and ties
+// go to the smaller position. Records of a point are written at the slot given by the pair's
+// rank.
 // ------------------------------------------------------------------------------------------
 template <int KMAX>
 struct TopList {
-  float a[KMAX];
-  int32_t idx[KMAX];
-  int32_t code[KMAX];
+  uint64_t k[KMAX];   // list keys, best first; 0 marks an empty slot
 };
+
+// List key of output i with value y: |y| bits << 32 | (0xffff - i) << 1 | sign. Keys compare as
+// integers in list order (|y| desc, i asc) with no ties, and carry the code (i, or i + D when
+// y < 0). Every key of a real output is > 0.
+__device__ __forceinline__ uint64_t list_key(float y, int32_t i) {
+  return ((uint64_t)__float_as_uint(fabsf(y)) << 32) | ((uint32_t)(0xffff - i) << 1) |
+         (y >= 0.0f ? 0u : 1u);
+}
+__device__ __forceinline__ float key_abs(uint64_t k) { return __uint_as_float((uint32_t)(k >> 32)); }
+__device__ __forceinline__ int32_t key_code(uint64_t k, int D) {
+  const int32_t i = 0xffff - (int32_t)(((uint32_t)k & 0x1ffffu) >> 1);
+  return (k & 1u) ? i + D : i;
+}
 
 template <int KMAX>
 __device__ __forceinline__ void toplist_init(TopList<KMAX>& t) {
 #pragma unroll
-  for (int s = 0; s < KMAX; ++s) {
-    t.a[s] = -1.0f;
-    t.idx[s] = 0x7fffffff;
-    t.code[s] = 0;
-  }
+  for (int s = 0; s < KMAX; ++s) t.k[s] = 0ull;
 }
 
-// Insert (a, i, code) keeping (a desc, i asc). Elements arrive in increasing i within a
-// lane, so a strict comparison keeps the earlier index ahead on ties.
+// Insert a key, keeping the list in descending key order (one compare-exchange per slot).
 template <int KMAX>
-__device__ __forceinline__ void toplist_insert(TopList<KMAX>& t, float a, int32_t i, int32_t c) {
-  float ca = a;
-  int32_t ci = i, cc = c;
+__device__ __forceinline__ void toplist_insert(TopList<KMAX>& t, uint64_t key) {
+  uint64_t c = key;
 #pragma unroll
   for (int s = 0; s < KMAX; ++s) {
-    const bool sw = ca > t.a[s];
-    const float na = sw ? t.a[s] : ca;
-    const int32_t ni = sw ? t.idx[s] : ci;
-    const int32_t nc = sw ? t.code[s] : cc;
-    t.a[s] = sw ? ca : t.a[s];
-    t.idx[s] = sw ? ci : t.idx[s];
-    t.code[s] = sw ? cc : t.code[s];
-    ca = na;
-    ci = ni;
-    cc = nc;
+    const bool sw = c > t.k[s];
+    const uint64_t lo = sw ? t.k[s] : c;
+    t.k[s] = sw ? c : t.k[s];
+    c = lo;
   }
-}
-
-// (a, i) beats (b, j) in list order.
-__device__ __forceinline__ bool list_before(float a, int32_t i, float b, int32_t j) {
-  return a > b || (a == b && i < j);
 }
 
 // Merge the per-lane lists of a G-lane group into lane-uniform group lists (all lanes of the
-// group end with the same list). K rounds of a group argmax; the winner drops its head.
+// group end with the same list). K rounds of a group argmax (keys are distinct); the winner drops
+// its head.
 template <int KMAX, int G>
 __device__ __forceinline__ void toplist_group_merge(TopList<KMAX>& t) {
   if constexpr (G > 1) {
     TopList<KMAX> out;
-    toplist_init(out);
-    const int g = threadIdx.x % G;
 #pragma unroll
     for (int r = 0; r < KMAX; ++r) {
-      float ba = t.a[0];
-      int32_t bi = t.idx[0], bc = t.code[0], bl = g;
+      uint64_t best = t.k[0];
 #pragma unroll
       for (int o = 1; o < G; o <<= 1) {
-        const float oa = __shfl_xor(ba, o, G);
-        const int32_t oi = __shfl_xor(bi, o, G);
-        const int32_t oc = __shfl_xor(bc, o, G);
-        const int32_t ol = __shfl_xor(bl, o, G);
-        if (list_before(oa, oi, ba, bi)) {
-          ba = oa;
-          bi = oi;
-          bc = oc;
-          bl = ol;
-        }
+        const uint32_t lo = __shfl_xor((uint32_t)best, o, G), hi = __shfl_xor((uint32_t)(best >> 32), o, G);
+        const uint64_t other = ((uint64_t)hi << 32) | lo;
+        best = other > best ? other : best;
       }
-      out.a[r] = ba;
-      out.idx[r] = bi;
-      out.code[r] = bc;
-      if (bl == g) {   // the winning lane drops its head
+      out.k[r] = best;
+      if (best != 0ull && t.k[0] == best) {   // the winning lane drops its head
 #pragma unroll
-        for (int s = 0; s + 1 < KMAX; ++s) {
-          t.a[s] = t.a[s + 1];
-          t.idx[s] = t.idx[s + 1];
-          t.code[s] = t.code[s + 1];
-        }
-        t.a[KMAX - 1] = -1.0f;
-        t.idx[KMAX - 1] = 0x7fffffff;
+        for (int s = 0; s + 1 < KMAX; ++s) t.k[s] = t.k[s + 1];
+        t.k[KMAX - 1] = 0ull;
       }
     }
     t = out;
@@ -132,21 +111,21 @@ __device__ __forceinline__ void select_pairs(const TopList<KMAX>& A, const TopLi
 #pragma unroll
       for (int j = 0; (i + 1) * (j + 1) <= KMAX; ++j) {
         if (i < lim && j < lim && (i + 1) * (j + 1) <= K) {
-          const float s = A.a[i] + B.a[j];
+          const float s = key_abs(A.k[i]) + key_abs(B.k[j]);
           int rank = 0;
 #pragma unroll
           for (int i2 = 0; i2 < KMAX; ++i2) {
 #pragma unroll
             for (int j2 = 0; (i2 + 1) * (j2 + 1) <= KMAX; ++j2) {
               if (i2 < lim && j2 < lim && (i2 + 1) * (j2 + 1) <= K) {
-                const float s2 = A.a[i2] + B.a[j2];
+                const float s2 = key_abs(A.k[i2]) + key_abs(B.k[j2]);
                 rank += (s2 > s || (s2 == s && (i2 < i || (i2 == i && j2 < j)))) ? 1 : 0;
               }
             }
           }
           if (rank < K) {
-            const bool keep = !(A.a[i] < thr) && !(B.a[j] < thr);
-            rb[rank] = keep ? (uint32_t)(A.code[i] * (2 * D) + B.code[j]) : kDropped;
+            const bool keep = !(key_abs(A.k[i]) < thr) && !(key_abs(B.k[j]) < thr);
+            rb[rank] = keep ? (uint32_t)(key_code(A.k[i], D) * (2 * D) + key_code(B.k[j], D)) : kDropped;
             rk[rank] = s;
           }
         }
@@ -155,17 +134,17 @@ __device__ __forceinline__ void select_pairs(const TopList<KMAX>& A, const TopLi
   } else {
     for (int i = 0; i < lim; ++i) {
       for (int j = 0; j < lim && (i + 1) * (j + 1) <= K; ++j) {
-        const float s = A.a[i] + B.a[j];
+        const float s = key_abs(A.k[i]) + key_abs(B.k[j]);
         int rank = 0;
         for (int i2 = 0; i2 < lim; ++i2) {
           for (int j2 = 0; j2 < lim && (i2 + 1) * (j2 + 1) <= K; ++j2) {
-            const float s2 = A.a[i2] + B.a[j2];
+            const float s2 = key_abs(A.k[i2]) + key_abs(B.k[j2]);
             rank += (s2 > s || (s2 == s && (i2 < i || (i2 == i && j2 < j)))) ? 1 : 0;
           }
         }
         if (rank < K) {
-          const bool keep = !(A.a[i] < thr) && !(B.a[j] < thr);
-          rb[rank] = keep ? (uint32_t)(A.code[i] * (2 * D) + B.code[j]) : kDropped;
+          const bool keep = !(key_abs(A.k[i]) < thr) && !(key_abs(B.k[j]) < thr);
+          rb[rank] = keep ? (uint32_t)(key_code(A.k[i], D) * (2 * D) + key_code(B.k[j], D)) : kDropped;
           rk[rank] = s;
         }
       }
@@ -239,7 +218,7 @@ __global__ __launch_bounds__(64) void hash_build_kernel(
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const int i = g * E + e;
-        if (i < D) toplist_insert(tl, fabsf(v[e]), i, v[e] >= 0.0f ? i : i + D);
+        if (i < D) toplist_insert(tl, list_key(v[e], i));
       }
       toplist_group_merge<KMAX, G>(tl);
       if (f == 0) list0 = tl; else list1 = tl;
@@ -251,8 +230,8 @@ __global__ __launch_bounds__(64) void hash_build_kernel(
 #pragma unroll
       for (int s = 0; s < KMAX; ++s)
         if (s < K) {
-          rb[s] = !(list0.a[s] < thr) ? (uint32_t)list0.code[s] : kDropped;
-          rk[s] = list0.a[s];
+          rb[s] = !(key_abs(list0.k[s]) < thr) ? (uint32_t)key_code(list0.k[s], D) : kDropped;
+          rk[s] = key_abs(list0.k[s]);
         }
     } else {
       select_pairs<KMAX>(list0, list1, K, D, thr, rb, rk);

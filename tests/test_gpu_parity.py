@@ -1,16 +1,21 @@
 """GPU path (C ABI) against the CPU oracle, element by element, on seeded synthetic inputs.
 
 Bar: hash lists, build records, CSR tables, probe sets and candidate counts are bit-exact;
-top-k ids are identical except where two candidates' float64 scores lie within the float32
-reduction bound (adjudicated near-ties, counted); float32 scores are within 1e-6 relative of
-the oracle's float64 dot products, or within the float32 reduction bound where that is looser.
+float32 scores are within 1e-6 relative of the oracle's float64 dot products (1e-6 of
+sum |q_j x_j| where |s| < 0.1); top-k ids are identical except at positions where the two ids'
+float64 scores lie within twice that bound (adjudicated near-ties: counted, printed at the end of
+the session, at most 0.1% of the compared positions).
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
 import synthdata
+from _parity import check_topk, score_tol, swap_budget
+from golden.make_fullsize_oracle import probe_digest, table_digest
 from oracle import falconn as O
 
 pytestmark = pytest.mark.gpu
@@ -85,52 +90,6 @@ def built(name):
         torch.cuda.synchronize()
         _cache[name] = (w, oi, h, Xd, Qd)
     return _cache[name]
-
-
-EPC = {"fp32": 4, "bf16": 8, "fp8": 16}     # elements per 16-byte chunk of a stored row
-
-
-def lane_layout(d, store="fp32"):
-    """(G lanes per row, C chunks per lane) of the gather kernel for rows of d elements."""
-    nc = -(-d // EPC[store])
-    for C in (1, 2, 4):
-        if nc <= 8 * C:
-            return 8, C
-    if nc <= 64:
-        return 64, 1
-    return 64, (2 if nc <= 128 else 4)
-
-
-def score_tol(s64, sabs, d, store="fp32"):
-    """FP32 error bound of one score: a chain of EPC*C fused multiply-adds per lane, log2(G)
-    tree levels, one rounding of slack (and the FP8 row-scale product), each at most 2^-24
-    relative to sum |q_j x_j|; never tighter than 1e-6 relative."""
-    G, C = lane_layout(d, store)
-    n = EPC[store] * C + math.log2(G) + 1 + (1 if store == "fp8" else 0)
-    return np.maximum(1e-6 * np.abs(s64), n * 2.0 ** -24 * sabs)
-
-
-def check_topk(X, Q, gi, gs, oi_ids, oi_sc, k, d, store="fp32"):
-    """ids equal up to adjudicated near-ties; scores within tolerance. Returns #swaps."""
-    gi = gi.astype(np.int64)
-    swaps = 0
-    X64 = X.astype(np.float64)
-    for r in range(Q.shape[0]):
-        q = Q[r].astype(np.float64)
-        valid = gi[r] >= 0
-        assert np.array_equal(valid, oi_ids[r] >= 0), (r, gi[r], oi_ids[r])
-        ids = gi[r][valid]
-        assert len(set(ids.tolist())) == len(ids)
-        s64 = X64[ids] @ q
-        sabs = np.abs(X64[ids] * q).sum(1)
-        tol = score_tol(s64, sabs, d, store)
-        assert np.all(np.abs(gs[r][valid].astype(np.float64) - s64) <= tol), r
-        assert np.all(np.isneginf(gs[r][~valid]))
-        if not np.array_equal(gi[r], oi_ids[r]):
-            # the r-th best value must agree within the float32 bound
-            assert np.all(np.abs(s64 - oi_sc[r][valid]) <= 2 * tol + 1e-300), (r, gi[r], oi_ids[r])
-            swaps += int(np.sum(gi[r] != oi_ids[r]))
-    return swaps
 
 
 # ----------------------------------------------------------------------------------------------
@@ -286,6 +245,33 @@ def test_build_records_bit_exact(name):
         np.testing.assert_array_equal(k.cpu().numpy().view(np.uint32), ok.view(np.uint32))
 
 
+@pytest.mark.parametrize("d,D,l,ip", [(128, 128, 2, 3), (128, 128, 1, 1), (64, 32, 2, 10),
+                                      (300, 256, 2, 3), (300, 256, 2, 16), (20, 16, 1, 4)])
+def test_build_records_exact_ties_bit_exact(d, D, l, ip):
+    """Build records of vectors whose projections tie exactly (basis, constant and repeated-
+    coordinate vectors; zero), so equal |y| meet at the top-iProbes boundary and the list order
+    rests on the index. For d = 128 the data also holds two points of the headline data set whose
+    second function in table 6 of the seed-42 index ties at list positions 2 and 3 (the build
+    once took the larger index first there)."""
+    X = [_near_tie_vectors(d, np.random.default_rng(d + ip))]
+    if d == 128:
+        X.insert(0, synthdata.workload("c2_cluster_1m_d128").X[[648304, 786308]])
+    X = np.concatenate(X).astype(np.float32)
+    L = 8 if d != 128 else 100
+    h = F().fpp_build_index(torch.from_numpy(X).cuda(), L, D, 0.5, ip, 42, l=l)
+    try:
+        S = O.rotation_signs(42, L, l, O.padded_dim(d, D))
+        for t in range(L):
+            b, k = F().fpp_debug_build_records(h, t)
+            torch.cuda.synchronize()
+            lists = [O.hash_lists(X, S[t, f], D) for f in range(l)]
+            ob, ok = O.top_pairs(lists, D, ip)
+            np.testing.assert_array_equal(b.cpu().numpy().astype(np.int64), ob, err_msg=f"table {t}")
+            np.testing.assert_array_equal(k.cpu().numpy().view(np.uint32), ok.view(np.uint32))
+    finally:
+        F().fpp_free_index(h)
+
+
 @pytest.mark.parametrize("name", list(CONFIGS))
 def test_tables_bit_exact(name):
     w, oi, h, Xd, Qd = built(name)
@@ -313,6 +299,22 @@ def test_probe_sets_bit_exact(name):
             assert sorted(g[r].tolist()) == sorted(ref.tolist()), (qp, r)
 
 
+@pytest.mark.parametrize("name", ["l2_clustered", "c1_gauss_10k_d64", "manyL_d24_L40", "l1_L24_D16",
+                                  "wideD_d20_D64"])
+def test_probe_sets_near_ties_bit_exact(name):
+    """Probe budgets up to 2L take the fused hash-and-select kernel; vectors whose projections
+    tie (zero, constant, basis vectors) emit more outputs than it holds, so those queries are
+    finished by the list-based kernels. Every probe set is bit-exact either way."""
+    w, oi, h, Xd, Qd = built(name)
+    V = np.concatenate([w["Q"][:10], _near_tie_vectors(w["X"].shape[1], np.random.default_rng(11))])
+    Vd = torch.from_numpy(V).cuda()
+    for qp in sorted({1, max(1, w["L"] // 2), w["L"], 2 * w["L"], 2 * w["L"] + 1}):
+        g = F().fpp_debug_probes(h, Vd, qp).cpu().numpy()
+        for r in range(V.shape[0]):
+            ref = O.probes(oi, V[r], qp)
+            assert sorted(g[r].tolist()) == sorted(ref.tolist()), (qp, r)
+
+
 @pytest.mark.parametrize("name", ["c1_gauss_10k_d64", "l2_clustered", "p512_d300_D256", "l1_D8_iprobes3"])
 def test_gap_probe_sets_bit_exact(name):
     """Plain Falconn's gap score: probe sets bit-exact, and queries match the oracle."""
@@ -326,7 +328,8 @@ def test_gap_probe_sets_bit_exact(name):
     qp = 4 * w["L"]
     ids, sc = F().fpp_query(h, Qd, 10, qp, probe_score="gap")
     oids, osc, _ = O.query(oi, w["Q"], 10, qp, "gap")
-    assert check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, w["X"].shape[1]) <= 3
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    assert swaps <= swap_budget(ids.numel()), swaps
 
 
 @pytest.mark.parametrize("name", list(CONFIGS))
@@ -337,8 +340,8 @@ def test_query_fp32_matches_oracle(name, k):
     ids, sc, st = F().fpp_query(h, Qd, k, qp, stats=True)
     oids, osc, ost = O.query(oi, w["Q"], k, qp)
     np.testing.assert_array_equal(st.cpu().numpy(), ost)
-    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, k, w["X"].shape[1])
-    assert swaps <= max(2, w["Q"].shape[0] * k // 200), swaps
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    assert swaps <= swap_budget(ids.numel()), swaps
 
 
 @pytest.mark.parametrize("qp", [2000, 10 ** 6])
@@ -350,7 +353,8 @@ def test_query_many_candidates_uses_bitmap_dedup(qp):
     st = st.cpu().numpy()
     np.testing.assert_array_equal(st, ost)
     assert st[:, 2].max() > 3072
-    assert check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 100, 128) <= 20
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    assert swaps <= swap_budget(ids.numel()), swaps
     # a second call reuses the (cleared) bitmaps
     ids2, sc2 = F().fpp_query(h, Qd, 100, qp)
     assert torch.equal(ids, ids2) and torch.equal(sc, sc2)
@@ -387,7 +391,8 @@ def test_query_c1_published_qprobes():
     for qp in (40, 4):
         ids, sc = F().fpp_query(h, Qd, 10, qp)
         oids, osc, _ = O.query(oi, w["Q"], 10, qp)
-        assert check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 64) <= 2
+        swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+        assert swaps <= swap_budget(ids.numel()), swaps
 
 
 # ----------------------------------------------------------------------------------------------
@@ -455,7 +460,7 @@ def test_padding_when_fewer_candidates_than_k():
         Qd = torch.from_numpy(Q).cuda()
         ids, sc = F().fpp_query(h, Qd, 512, 1)
         oids, osc, _ = O.query(oi, Q, 512, 1)
-        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 512, 16)
+        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
         assert (ids.cpu().numpy() == -1).any()
     finally:
         F().fpp_free_index(h)
@@ -469,7 +474,7 @@ def test_n_smaller_than_k_and_full_probing():
         Qd = torch.from_numpy(Q).cuda()
         ids, sc = F().fpp_query(h, Qd, 10, 10 ** 6)
         oids, osc, _ = O.query(oi, Q, 10, 10 ** 6)
-        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 8)
+        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
     finally:
         F().fpp_free_index(h)
 
@@ -489,7 +494,7 @@ def test_duplicate_points_and_zero_query():
         Qd = torch.from_numpy(Q).cuda()
         ids, sc = F().fpp_query(h, Qd, 10, 64)
         oids, osc, _ = O.query(oi, Q, 10, 64)
-        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 32)
+        check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
         got = ids.cpu().numpy()[0][:3].tolist()
         assert got == [5, 10, 11] or oids[0][:3].tolist() != [5, 10, 11]
         np.testing.assert_array_equal(ids.cpu().numpy()[0], oids[0])
@@ -595,7 +600,8 @@ def test_heuristic_builds_bit_exact(name):
         Qd = torch.from_numpy(Q).cuda()
         ids, sc = F().fpp_query(h, Qd, 10, 8 * L)
         oids, osc, _ = O.query(oi, Q, 10, 8 * L)
-        assert check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 64) <= 3
+        swaps = check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+        assert swaps <= swap_budget(ids.numel()), swaps
     finally:
         F().fpp_free_index(h)
 
@@ -620,8 +626,8 @@ def test_query_low_precision_with_rerank(name, store):
     k, qp = 10, 8 * w["L"]
     ids, sc = F().fpp_query(h, Qd, k, qp, store=store)
     oids, osc, _ = O.query_reranked(oi, w["Q"], k, qp, R=100, storage=store)
-    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, k, w["X"].shape[1])
-    assert swaps <= max(3, w["Q"].shape[0] * k // 50), swaps
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    assert swaps <= swap_budget(ids.numel()), swaps
     # rerank scores equal the exact FP32 path's scores for the same ids
     fi, fs = F().fpp_query(h, Qd, k, qp)
     same = (ids == fi).all(dim=1)
@@ -646,8 +652,8 @@ def test_query_low_precision_without_rerank(name, store):
     for r in range(m):
         cand = O.candidates(oi, O.probes(oi, w["Q"][r], qp))
         oids[r], osc[r] = O.topk_order(deq[cand] @ w["Q"][r].astype(np.float64), cand, k)
-    swaps = check_topk(deq, w["Q"], gi, gs, oids, osc, k, w["X"].shape[1], store)
-    assert swaps <= max(3, m * k // 50), swaps
+    swaps = check_topk(deq, w["Q"], gi, gs, oids, osc)
+    assert swaps <= swap_budget(gi.size), swaps
 
 
 def test_rerank_of_exactly_k_is_a_reorder_with_exact_scores():
@@ -665,7 +671,7 @@ def test_rerank_of_exactly_k_is_a_reorder_with_exact_scores():
             x64 = w["X"][v].astype(np.float64)
             q64 = w["Q"][r].astype(np.float64)
             s64 = x64 @ q64
-            tol = score_tol(s64, np.abs(x64 * q64).sum(1), d)
+            tol = score_tol(s64, np.abs(x64 * q64).sum(1))
             assert np.all(np.abs(gs[r][: len(v)] - s64) <= tol)
             assert np.all(np.diff(gs[r][: len(v)]) <= 0)
 
@@ -696,55 +702,89 @@ def test_simhash_store_and_queries(D, nf, l):
         # with the FP32 rerank of a short list of 100
         ids, sc = F().fpp_query(h, Qd, 10, qp, store="simhash", rerank_R=100)
         oids, osc, _ = O.query_reranked(oi, Q, 10, qp, R=100, storage="simhash", simhash_functions=nf)
-        assert check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc, 10, 64) <= 3
+        swaps = check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+        assert swaps <= swap_budget(ids.numel()), swaps
     finally:
         F().fpp_free_index(h)
 
 
 # ----------------------------------------------------------------------------------------------
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def _compare_fullsize(g, w, h, Qd):
+    """Tables, probe sets, candidate counts and top-k of the sampled queries against the oracle's
+    stored values; every query call covers the whole batch (the benchmark's launch shape)."""
+    rows = np.asarray(g["queries"], dtype=np.int64)
+    print(f"{g['workload']}: {g['L']} tables against the oracle", flush=True)
+    sizes = F().fpp_index_table_sizes(h)
+    for t, rec in enumerate(g["tables"]):
+        off, ids = F().fpp_debug_export_table(h, t)
+        assert sizes[t] == rec["size"] and int(np.max(np.diff(off))) == rec["max_bucket"], t
+        assert table_digest(off, ids) == rec["sha256"], t
+    Qs = Qd[torch.from_numpy(rows).cuda()].contiguous()
+    for qp, ref in g["fp32"].items():
+        print(f"{g['workload']}: FP32 path, qProbes {qp}", flush=True)
+        gi, gs, st = F().fpp_query(h, Qd, 10, int(qp), stats=True)
+        gi, gs, st = gi.cpu().numpy()[rows], gs.cpu().numpy()[rows], st.cpu().numpy()[rows]
+        np.testing.assert_array_equal(st, np.asarray(ref["stats"]))
+        swaps = check_topk(w.X, w.Q[rows], gi, gs, np.asarray(ref["ids"]), np.asarray(ref["scores"]),
+                           label=f"{g['workload']} fp32 qProbes={qp}")
+        assert swaps <= swap_budget(gi.size), swaps
+        if "probe_sha256" in ref:
+            pr = F().fpp_debug_probes(h, Qs, int(qp)).cpu().numpy()
+            assert [probe_digest(p) for p in pr] == ref["probe_sha256"]
+    for store, ref in g["rerank"].items():
+        qp = int(ref["qProbes"])
+        print(f"{g['workload']}: {store} + rerank of {ref['R']}, qProbes {qp}", flush=True)
+        gi, gs = F().fpp_query(h, Qd, 10, qp, store=store, rerank_R=int(ref["R"]))
+        gi, gs = gi.cpu().numpy()[rows], gs.cpu().numpy()[rows]
+        swaps = check_topk(w.X, w.Q[rows], gi, gs, np.asarray(ref["ids"]), np.asarray(ref["scores"]),
+                           label=f"{g['workload']} {store}+rerank qProbes={qp}")
+        assert swaps <= swap_budget(gi.size), swaps
+
+
 @pytest.mark.timeout(600)
-def test_full_size_c2_sampled():
-    """n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3, in the launch
-    configuration of the benchmark: sampled tables bit-exact, sampled queries' probes bit-exact,
-    and their top-k equal to exact search over the candidates those probes select."""
+def test_full_size_c2_against_oracle():
+    """The headline index (n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3)
+    against the oracle's own index and answers (stored by tests/golden/make_fullsize_oracle.py):
+    all 100 tables bit-exact, and for 200 queries spread over the 10,000-query batch the probe
+    sets (50 in total), the candidate counts and the FP32 top-10 at 50 probes and at 50 per
+    table, and the BF16 and FP8 paths with the FP32 rerank of 100."""
+    g = _golden("c2_full_oracle.json")
     w = synthdata.workload("c2_cluster_1m_d128")
+    assert (g["n"], g["d"], g["L"], g["D"]) == (w.X.shape[0], w.X.shape[1], w.L, w.D)
     Xd = torch.from_numpy(w.X).cuda()
-    h = F().fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l)
+    h = F().fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, g["seed"], l=w.l, stores=("bf16", "fp8"))
     try:
-        S = O.rotation_signs(42, w.L, w.l, 128)
-        np.testing.assert_array_equal(F().fpp_debug_signs(h), S)
-        for t in (w.L - 1,):     # the last table: its ids sit after every other table's
-            print(f"full-size c2: oracle table {t}", flush=True)
-            off, ids = F().fpp_debug_export_table(h, t)
-            ooff, oids, _ = O.build_table(w.X, S[t], w.D, w.l, w.alpha, w.iProbes)
-            np.testing.assert_array_equal(off, ooff)
-            np.testing.assert_array_equal(ids, oids)
-        Qd = torch.from_numpy(w.Q).cuda()
-        tables = {}
-        shell = O.Index(X=w.X, L=w.L, D=w.D, l=w.l, P=128, alpha=w.alpha, iProbes=w.iProbes, seed=42, signs=S)
-        NB = O.n_buckets(w.D, w.l)
-        for qp in (50, 50 * w.L):     # the benchmark's total, and 50 per table
-            print(f"full-size c2: qProbes {qp}", flush=True)
-            gi, gs, st = F().fpp_query(h, Qd, 10, qp, stats=True)
-            gi, gs, st = gi.cpu().numpy(), gs.cpu().numpy(), st.cpu().numpy()
-            for r in (0, 1, 2, w.Q.shape[0] - 1):
-                pr = O.probes(shell, w.Q[r], qp)
-                gp = F().fpp_debug_probes(h, Qd[r:r + 1].contiguous(), qp).cpu().numpy()[0]
-                assert sorted(gp.tolist()) == sorted(pr.tolist())
-                cand = []
-                for p in pr:
-                    t, b = divmod(int(p), NB)
-                    if t not in tables:
-                        tables[t] = F().fpp_debug_export_table(h, t)
-                    off, ids = tables[t]
-                    cand.append(ids[off[b]:off[b + 1]])
-                cand = np.unique(np.concatenate(cand).astype(np.int64))
-                assert st[r, 2] == len(cand)
-                s64 = O.scores_f64(w.X, w.Q[r], cand)
-                ri, rs = O.topk_order(s64, cand, 10)
-                check_topk(w.X, w.Q[r:r + 1], gi[r:r + 1], gs[r:r + 1], ri[None], rs[None], 10, 128)
+        np.testing.assert_array_equal(F().fpp_debug_signs(h), O.rotation_signs(g["seed"], w.L, w.l, 128))
+        _compare_fullsize(g, w, h, torch.from_numpy(w.Q).cuda())
     finally:
         F().fpp_free_index(h)
+
+
+@pytest.mark.timeout(900)
+def test_c5_shape_against_oracle():
+    """The large workload's data and table shape (n = 10M, d = 96 zero-padded to P = 256, D = 256,
+    l = 2, alpha = 0.1, iProbes = 2) with 4 of its 64 tables: every table bit-exact against the
+    oracle's, and for 200 of the 100,000 queries (one launch) the probe sets at 100 probes per
+    table, the candidate counts, the FP32 top-10 and the FP8 path with the FP32 rerank of 100."""
+    g = _golden("c5_shape_oracle.json")
+    print("c5 shape: drawing 10M x 96", flush=True)
+    w = synthdata.workload("c5_cluster_10m_d96")
+    assert (g["n"], g["d"], g["D"]) == (w.X.shape[0], w.X.shape[1], w.D)
+    Xd = torch.from_numpy(w.X).cuda()
+    h = F().fpp_build_index(Xd, g["L"], w.D, w.alpha, w.iProbes, g["seed"], l=w.l, stores=("fp8",))
+    try:
+        _compare_fullsize(g, w, h, torch.from_numpy(w.Q).cuda())
+    finally:
+        F().fpp_free_index(h)
+        del Xd
 
 
 @pytest.mark.timeout(600)

@@ -1,27 +1,39 @@
 """Serving loop (continuous batching) through the C ABI: every request's result equals the same
-query run alone, admission by scratch bytes neither loses nor duplicates requests, requests larger
-than the pool are rejected, and timestamps are consistent."""
+query run alone and the oracle's answer, admission by scratch bytes neither loses nor duplicates
+requests, requests larger than the pool are rejected, a failing batch fails only its own requests,
+and timestamps are consistent."""
 import time
 
 import numpy as np
 import pytest
 
 import synthdata
+from _parity import check_topk, swap_budget
+from oracle import falconn as O
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
 
+X_SERVE, Q_SERVE = None, None
+
+
 @pytest.fixture(scope="module")
 def env():
     import paper_2206_01382_amd as F
+    global X_SERVE, Q_SERVE
     assert torch.cuda.is_available()
-    X, Q = synthdata.clustered_sphere(30_000, 64, 300, 40, 0.3, seed=11)
-    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    X_SERVE, Q_SERVE = synthdata.clustered_sphere(30_000, 64, 300, 40, 0.3, seed=11)
+    Xd, Qd = torch.from_numpy(X_SERVE).cuda(), torch.from_numpy(Q_SERVE).cuda()
     h = F.fpp_build_index(Xd, 8, 32, 0.3, 3, 77, l=2, stores=("bf16",))
     yield F, h, Xd, Qd
     F.fpp_free_index(h)
+
+
+@pytest.fixture(scope="module")
+def oracle_index(env):
+    return O.build_index(X_SERVE, 8, 32, 0.3, 3, 77, l=2)
 
 
 def _requests(rng, m_total, n_req, ks, qps):
@@ -52,7 +64,10 @@ def _run(F, sv, Qd, reqs, kmax, pace_s=0.0):
 
 
 @pytest.mark.parametrize("store", ["fp32", "bf16"])
-def test_results_alone_equal_results_in_the_mix(env, store):
+def test_results_alone_equal_results_in_the_mix(env, oracle_index, store):
+    """Served in mixed batches, each request equals the same query run alone (bit-identical)
+    and the oracle's answer (FP32: Algorithm 1 and FP64 scores; BF16: the FP64 rerank of the
+    short list of max(100, 2k) by the approximate score), under the comparison rule."""
     F, h, Xd, Qd = env
     rng = np.random.default_rng(1)
     reqs = _requests(rng, Qd.shape[0], 120, (1, 10, 100), (8, 40, 200))
@@ -64,10 +79,19 @@ def test_results_alone_equal_results_in_the_mix(env, store):
         F.fpp_server_destroy(sv)
     assert st["completed"] == len(reqs) and st["failed"] == 0
     assert st["batches"] < len(reqs)              # requests were batched together
+    swaps = results = 0
     for (row, m, k, qp), (ids, sc), (status, ts, td) in zip(reqs, outs, stamps):
         assert status == 0 and 0 < ts <= td
         ri, rs = F.fpp_query(h, Qd[row:row + m].contiguous(), k, qp, store=store)
         assert torch.equal(ids, ri) and torch.equal(sc, rs)
+        Qr = Q_SERVE[row:row + m]
+        if store == "fp32":
+            oi, osc, _ = O.query(oracle_index, Qr, k, qp)
+        else:
+            oi, osc, _ = O.query_reranked(oracle_index, Qr, k, qp, R=max(100, 2 * k), storage=store)
+        swaps += check_topk(X_SERVE, Qr, ids.cpu().numpy(), sc.cpu().numpy(), oi, osc)
+        results += m * k
+    assert swaps <= swap_budget(results), swaps
 
 
 def test_small_pool_admission_and_oversized_requests(env):
@@ -196,3 +220,32 @@ def test_replay_submits_on_schedule_and_matches_direct_queries(env):
         ri, rs = F.fpp_query(h, Qd[r:r + mm].contiguous(), kk, int(qp[i]))
         assert torch.equal(ids[o:o + mm * kk].view(mm, kk), ri)
         assert torch.equal(sc[o:o + mm * kk].view(mm, kk), rs)
+
+
+def test_failed_batch_fails_only_its_requests(env):
+    """A batch that fails on the device side (forced from the host after its first kernel is on
+    the stream) completes its requests with FPP_EHIP and returns its scratch; the loop then
+    serves later requests correctly."""
+    F, h, Xd, Qd = env
+    sv = F.fpp_server_create(h, scratch_bytes=64 << 20, n_streams=2, max_batch=16)
+    try:
+        ids = torch.full((3, 10), -7, dtype=torch.int32, device="cuda")
+        sc = torch.full((3, 10), 7.0, dtype=torch.float32, device="cuda")
+        F.fpp_server_debug_fail_batches(sv, 1)
+        t = F.fpp_server_submit(sv, Qd.data_ptr(), 3, 10, 40, ids.data_ptr(), sc.data_ptr())
+        st, ts, td = F.fpp_server_wait(sv, t, 60_000)
+        assert st == F.FPP_EHIP and td >= ts > 0
+        stats = F.fpp_server_get_stats(sv)
+        assert stats["failed"] == 1 and stats["completed"] == 0
+        reqs = [(r, 2, 10, 40) for r in range(0, 40, 2)]
+        outs, stamps, _ = _run(F, sv, Qd, reqs, 10)
+        stats = F.fpp_server_get_stats(sv)
+        assert stats["completed"] == len(reqs) and stats["failed"] == 1
+        for (row, m, k, qp), (i2, s2), (status, _, _) in zip(reqs, outs, stamps):
+            assert status == 0
+            ri, rs = F.fpp_query(h, Qd[row:row + m].contiguous(), k, qp)
+            assert torch.equal(i2, ri) and torch.equal(s2, rs)
+        with pytest.raises(F.FppError):
+            F.fpp_server_debug_fail_batches(sv, -1)
+    finally:
+        F.fpp_server_destroy(sv)
