@@ -50,6 +50,15 @@ std::vector<uint32_t> make_sign_masks(uint64_t seed, int L, int l, int P) {
   return m;
 }
 
+std::vector<uint32_t> pack_sign_bits(const std::vector<uint32_t>& masks, int L, int l, int P) {
+  const int wpr = std::max(1, P / 32);
+  std::vector<uint32_t> w((size_t)L * l * 3 * wpr, 0u);
+  for (size_t fr = 0; fr < (size_t)L * l * 3; ++fr)
+    for (int j = 0; j < P; ++j)
+      if (masks[fr * P + j]) w[fr * wpr + j / 32] |= 1u << (j % 32);
+  return w;
+}
+
 int64_t keep_count_host(int64_t B, int64_t A, int K, int rounding) {
   const uint64_t den = (uint64_t)K * 1000000ull, num = (uint64_t)B * (uint64_t)A;
   return (int64_t)(rounding == 0 ? (num + den - 1) / den : num / den);
@@ -141,8 +150,8 @@ static int dalloc(T** p, size_t count, int64_t* acc) {
 
 static void free_index_memory(fpp_index* ix) {
   if (!ix) return;
-  void* ptrs[] = {ix->X, ix->Xbf16, ix->Xfp8, ix->fp8_scale, ix->sign_mask, ix->offsets, ix->ids,
-                  ix->center_vec, ix->Xsig};
+  void* ptrs[] = {ix->X, ix->Xbf16, ix->Xfp8, ix->fp8_scale, ix->sign_mask, ix->sign_bits,
+                  ix->offsets, ix->ids, ix->center_vec, ix->Xsig};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (ix->gbm) (void)hipFree(ix->gbm);
@@ -298,6 +307,9 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   const std::vector<uint32_t> masks = make_sign_masks(seed, L, o.l, ix->P);
   FPP_TRY(dalloc(&ix->sign_mask, masks.size(), &bytes));
   FPP_HIP(hipMemcpyAsync(ix->sign_mask, masks.data(), masks.size() * 4, hipMemcpyHostToDevice, s));
+  const std::vector<uint32_t> bits = pack_sign_bits(masks, L, o.l, ix->P);
+  FPP_TRY(dalloc(&ix->sign_bits, bits.size(), &bytes));
+  FPP_HIP(hipMemcpyAsync(ix->sign_bits, bits.data(), bits.size() * 4, hipMemcpyHostToDevice, s));
   FPP_TRY(dalloc(&ix->offsets, (size_t)L * (NB + 1), &bytes));
   FPP_TRY(dalloc(&ix->ids, (size_t)id_cap, &bytes));
 
@@ -460,10 +472,21 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     FPP_TRY(mark());
     // the SimHash signature reads every code; probe selection only a prefix of each list
     const int W = qs.store == FPP_STORE_SIMHASH ? ix->D : probe_list_len(ix, ly.qcap);
-    FPP_HIP(launch_hash_query(ix, Qc, mc, d, la, lc, W, s));
-    FPP_TRY(mark());
-    FPP_HIP(launch_probe_select(ix, la, lc, mc, qs.qp_dev ? qs.qp_dev + c0 : nullptr, qs.qp_uniform,
-                                ly.qcap, qs.probe_score, probes, np, s));
+    const int32_t* qp_c = qs.qp_dev ? qs.qp_dev + c0 : nullptr;
+    if (hash_probe_applies(ix, ly.qcap, qs.probe_score, qs.store)) {
+      // hashing and selection in one kernel; the list-based kernels finish only the queries it
+      // leaves (nprobe < 0)
+      FPP_HIP(launch_hash_probe(ix, Qc, mc, d, qp_c, qs.qp_uniform, ly.qcap, probes, np, s));
+      FPP_HIP(launch_hash_query(ix, Qc, mc, d, la, lc, W, s, np));
+      FPP_TRY(mark());
+      FPP_HIP(launch_probe_select(ix, la, lc, mc, qp_c, qs.qp_uniform, ly.qcap, qs.probe_score, probes,
+                                  np, s, true));
+    } else {
+      FPP_HIP(launch_hash_query(ix, Qc, mc, d, la, lc, W, s));
+      FPP_TRY(mark());
+      FPP_HIP(launch_probe_select(ix, la, lc, mc, qp_c, qs.qp_uniform, ly.qcap, qs.probe_score, probes,
+                                  np, s));
+    }
     FPP_TRY(mark());
     ScoreArgs a{};
     a.Q = Qc;
@@ -861,8 +884,15 @@ int fpp_debug_probes(const fpp_index* ix, const float* Q, int64_t m, int32_t qPr
   FPP_TRY(sc.get(&lc, (size_t)m * LFD));
   FPP_TRY(sc.get(&pr, (size_t)m * qcap));
   FPP_TRY(sc.get(&np, (size_t)m));
-  FPP_HIP(launch_hash_query(ix, Q, m, ix->d, la, lc, probe_list_len(ix, qcap), s));
-  FPP_HIP(launch_probe_select(ix, la, lc, m, nullptr, qProbes, qcap, probe_score, pr, np, s));
+  // the same kernels as the query path
+  if (hash_probe_applies(ix, qcap, probe_score, FPP_STORE_FP32)) {
+    FPP_HIP(launch_hash_probe(ix, Q, m, ix->d, nullptr, qProbes, qcap, pr, np, s));
+    FPP_HIP(launch_hash_query(ix, Q, m, ix->d, la, lc, probe_list_len(ix, qcap), s, np));
+    FPP_HIP(launch_probe_select(ix, la, lc, m, nullptr, qProbes, qcap, probe_score, pr, np, s, true));
+  } else {
+    FPP_HIP(launch_hash_query(ix, Q, m, ix->d, la, lc, probe_list_len(ix, qcap), s));
+    FPP_HIP(launch_probe_select(ix, la, lc, m, nullptr, qProbes, qcap, probe_score, pr, np, s));
+  }
   std::vector<uint32_t> h((size_t)m * qcap);
   std::vector<int32_t> hn((size_t)m);
   FPP_HIP(hipMemcpyAsync(h.data(), pr, h.size() * 4, hipMemcpyDeviceToHost, s));

@@ -69,6 +69,8 @@ struct fpp_index {
   int32_t ldsig = 0;              // signature row stride in 32-bit words (multiple of 4)
   const float* Xh = nullptr;      // hashing input of the build kernels ([n][ldx]): X, or X - c
   uint32_t* sign_mask = nullptr;  // device [L][l][3][P]: 0 or 0x80000000 (xor mask of the sign)
+  uint32_t* sign_bits = nullptr;  // device [L][l][3][max(1, P / 32)]: bit j % 32 of word j / 32 set
+                                  // when element j of the diagonal is -1
   uint32_t* offsets = nullptr;    // device [L][NB + 1], absolute positions into ids
   int32_t* ids = nullptr;         // device [total_ids]
 
@@ -91,6 +93,8 @@ namespace fpp {
 // Host-side helpers
 // ----------------------------------------------------------------------------------------------
 std::vector<uint32_t> make_sign_masks(uint64_t seed, int L, int l, int P);
+// The same signs packed 32 to a word (layout of fpp_index::sign_bits).
+std::vector<uint32_t> pack_sign_bits(const std::vector<uint32_t>& masks, int L, int l, int P);
 int64_t keep_count_host(int64_t B, int64_t alpha_micro, int iProbes, int rounding);
 
 // ----------------------------------------------------------------------------------------------
@@ -105,8 +109,17 @@ hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_
 // Query-side hash: sorted lists for m vectors (row stride ldv floats) and all L*l functions.
 //   la: [m][L*l][D] float32, lc: [m][L*l][D] uint16 codes. Entries [0, W) of every list are
 //   written (1 <= W <= D; the kernel may write up to a multiple of its per-lane run past W).
+//   skip (optional, device [m]): vectors with skip[q] >= 0 are left out.
 hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int ldv, float* la,
-                             uint16_t* lc, int W, hipStream_t s);
+                             uint16_t* lc, int W, hipStream_t s, const int32_t* skip = nullptr);
+
+// Fused query hashing and probe selection (probe budgets up to 2L, D == P <= 256, probe score
+// FPP_PROBE_SUM): probes [m][qcap] and nprobe [m] as launch_probe_select writes them; a query the
+// kernel cannot finish gets nprobe = -1 and is left to the list-based kernels.
+bool hash_probe_applies(const fpp_index* ix, int32_t qp_max, int32_t probe_score, int32_t store);
+hipError_t launch_hash_probe(const fpp_index* ix, const float* V, int64_t m, int ldv,
+                             const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
+                             uint32_t* probes, int32_t* nprobe, hipStream_t s);
 
 // Per-table build passes over a chunk of Tc tables.
 struct BuildScratch {
@@ -139,9 +152,11 @@ double normal_quantile(double p);
 // Probe selection: probes [m][qcap] as absolute offset-array positions t * (NB + 1) + bucket;
 // nprobe[m] receives the count per query. It reads list entries [0, probe_list_len) only.
 int probe_list_len(const fpp_index* ix, int32_t qcap);
+// only_unfinished: select only for the queries whose nprobe is negative (after the fused kernel).
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc,
                                int64_t m, const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
-                               int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s);
+                               int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s,
+                               bool only_unfinished = false);
 
 // Candidate gather, dedup, scoring and top-k (plus the FP32 rerank of a short list).
 struct ScoreArgs {

@@ -9,6 +9,8 @@
 
 #include "fpp_internal.hpp"
 #include "lanes.hpp"
+#include "rotation.hpp"
+#include "wave_sort.hpp"
 
 namespace fpp {
 
@@ -23,59 +25,6 @@ FPP_DECL_BUILD(16)
 
 namespace {
 
-__device__ __forceinline__ float flip(float v, uint32_t mask) {
-  return __uint_as_float(__float_as_uint(v) ^ mask);
-}
-
-// ------------------------------------------------------------------------------------------
-// Query side, everything in registers. An item (vector, function) spans LPI = P / E lanes of a
-// wavefront; lane x of the item holds the E consecutive elements j = x * E + e. Butterfly stages
-// h < E pair register e with e ^ h inside the lane; stages h >= E pair lane x with x ^ (h / E)
-// (the lower lane adds, the upper subtracts) through DPP / row-swap lane exchanges; stages run in
-// the order h = 1, 2, ..., P/2.
-// The D keys (|y_i| bits << 32 | (0xffff - i) << 1 | sign) are then bitonic-sorted descending in
-// the same layout, which orders the list by (|y| desc, i asc) and carries the code bit.
-// ------------------------------------------------------------------------------------------
-template <int P>
-struct QLayout {
-  static constexpr int E = P < 16 ? P : (P / 64 > 16 ? P / 64 : 16);  // elements per lane
-  static constexpr int LPI = P / E;                                 // lanes per item
-  static constexpr int IPW = 64 / LPI;                              // items per wavefront
-};
-
-// v + (v of lane ^ X) * mul. For X = 1, 2 and 8 the partner is a DPP operand of one v_fmac (quad
-// permutes, and a rotation by 8 within a 16-lane row), for X = 4 after one DPP move; the s_nop
-// gives the two wait states a DPP read needs after a VALU write of its source. Other distances go
-// through xor_lanes.
-template <int X>
-__device__ __forceinline__ float fmac_xor(float v, float mul) {
-  float src = v;
-  if constexpr (X == 1) {
-    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
-  } else if constexpr (X == 2) {
-    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[2,3,0,1] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
-  } else if constexpr (X == 8) {
-    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 row_ror:8 row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
-  } else if constexpr (X == 4) {
-    // x ^ 4 = (x ^ 7) ^ 3: a half-row mirror move, then the quad reversal as the DPP operand
-    src = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));
-    asm volatile("s_nop 1\n\tv_fmac_f32_dpp %0, %1, %2 quad_perm:[3,2,1,0] row_mask:0xf bank_mask:0xf" : "+v"(v) : "v"(src), "v"(mul));
-  } else {
-    v = __builtin_fmaf(xor_lanes<X>(v), mul, v);
-  }
-  return v;
-}
-__device__ __forceinline__ float fmac_xor_n(float v, int x, float mul) {
-  switch (x) {
-    case 1: return fmac_xor<1>(v, mul);
-    case 2: return fmac_xor<2>(v, mul);
-    case 4: return fmac_xor<4>(v, mul);
-    case 8: return fmac_xor<8>(v, mul);
-    case 16: return fmac_xor<16>(v, mul);
-    default: return fmac_xor<32>(v, mul);
-  }
-}
-
 // Exact 64-bit list key: |y| bits << 32 | (0xffff - i) << 1 | sign; descending order of keys is
 // (|y| desc, i asc), and the low bit carries the code (i or i + D).
 __device__ __forceinline__ uint64_t exact_key(float y, int i) {
@@ -83,110 +32,11 @@ __device__ __forceinline__ uint64_t exact_key(float y, int i) {
   return ((uint64_t)__float_as_uint(fabsf(y)) << 32) | ((uint32_t)(0xffff - i) << 1) | neg;
 }
 
-__device__ __forceinline__ void ce_desc(uint32_t& a, uint32_t& b) {
-  const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
-  a = hi;
-  b = lo;
-}
 __device__ __forceinline__ void ce_desc(uint64_t& a, uint64_t& b) {
   const bool sw = a < b;
   const uint64_t x = sw ? b : a, y = sw ? a : b;
   a = x;
   b = y;
-}
-
-// Batcher's odd-even merge sort of n keys: comparator number c (in the network's order) as
-// lo * 1024 + hi, or -1 past the last one; all comparators keep the larger key at lo. 63
-// comparators for n = 16 and 19 for n = 8, against 80 and 24 for the bitonic network.
-constexpr int odd_even_pair(int n, int c) {
-  int idx = 0;
-  for (int p = 1; p < n; p <<= 1)
-    for (int k = p; k >= 1; k >>= 1)
-      for (int j = k % p; j + k < n; j += 2 * k)
-        for (int i = 0; i < k && i < n - j - k; ++i)
-          if ((i + j) / (2 * p) == (i + j + k) / (2 * p)) {
-            if (idx == c) return (i + j) * 1024 + (i + j + k);
-            ++idx;
-          }
-  return -1;
-}
-
-template <int E, int C = 0>
-__device__ __forceinline__ void lane_sort_desc(uint32_t (&key)[E]) {
-  constexpr int pr = odd_even_pair(E, C);
-  if constexpr (pr >= 0) {
-    ce_desc(key[pr / 1024], key[pr % 1024]);
-    lane_sort_desc<E, C + 1>(key);
-  }
-}
-
-// Bitonic merges (descending) in the item layout: lane li holds positions li * E + e. Every merge
-// of two sorted blocks of k / 2 starts by comparing position p with its mirror image p ^ (k - 1)
-// inside the block, which leaves two bitonic halves, every key of the first at least every key
-// of the second; half-cleaners at distances k / 4, ..., 1 then sort them. All compare-exchanges
-// keep the larger key in front, so no block runs in the other direction. Inside a lane the pairs
-// are registers; across lanes the partner comes from one lane exchange, and the median of (key,
-// partner, 0 or ~0) keeps the larger in the lower lane of the pair and the smaller in the upper.
-template <int E, int J>
-__device__ __forceinline__ void half_clean(uint32_t (&key)[E], int li) {
-  if constexpr (J > 0) {
-    if constexpr (J < E) {
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-        if ((e & J) == 0) ce_desc(key[e], key[e | J]);
-    } else {
-      const uint32_t lim = (li & (J / E)) == 0 ? 0xffffffffu : 0u;
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const uint32_t o = xor_lanes<J / E>(key[e]);
-        const uint32_t mx = key[e] > o ? key[e] : o, mn = key[e] > o ? o : key[e];
-        const uint32_t c = mx < lim ? mx : lim;
-        key[e] = mn > c ? mn : c;
-      }
-    }
-    half_clean<E, J / 2>(key, li);
-  }
-}
-
-template <int P, int E, int K>
-__device__ __forceinline__ void sort_levels(uint32_t (&key)[E], int li, int D) {
-  if constexpr (K <= P) {
-    if (K > D) return;
-    if constexpr (K <= E) {
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-        if ((e & (K >> 1)) == 0) ce_desc(key[e], key[e ^ (K - 1)]);
-    } else {
-      // position li * E + e pairs with (li ^ (K / E - 1)) * E + (E - 1 - e)
-      const uint32_t lim = (li & (K / (2 * E))) == 0 ? 0xffffffffu : 0u;
-#pragma unroll
-      for (int e = 0; e < E / 2; ++e) {
-        const uint32_t a = key[e], b = key[E - 1 - e];
-        const uint32_t pa = mirror_lanes<K / E - 1>(b), pb = mirror_lanes<K / E - 1>(a);
-        const uint32_t mxa = a > pa ? a : pa, mna = a > pa ? pa : a;
-        const uint32_t mxb = b > pb ? b : pb, mnb = b > pb ? pb : b;
-        const uint32_t ca = mxa < lim ? mxa : lim, cb = mxb < lim ? mxb : lim;
-        key[e] = mna > ca ? mna : ca;
-        key[E - 1 - e] = mnb > cb ? mnb : cb;
-      }
-    }
-    half_clean<E, K / 4>(key, li);
-    sort_levels<P, E, K * 2>(key, li, D);
-  }
-}
-
-// Sorts the first D keys (D a power of two <= P) descending: each lane's E keys with the odd-even
-// network when D >= E, then the bitonic merges across lanes (for D < E, bitonic merges only).
-template <int P, int E, int LPI>
-__device__ __forceinline__ void sort32_desc(uint32_t (&key)[E], int li, int j0, int D) {
-  (void)j0;
-  if (D >= E) {
-    // each lane's E keys with the odd-even network, then the bitonic merges across lanes
-    lane_sort_desc<E>(key);
-    sort_levels<P, E, 2 * E>(key, li, D);
-  } else {
-    sort_levels<P, E, 2>(key, li, D);
-  }
 }
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -381,17 +231,18 @@ constexpr int kHalf = 2;   // D == P / 2: the listed outputs are redistributed o
 
 // VEC: rows of V are 16-byte aligned and d % 4 == 0. MODE: kAnyD, kFull or kHalf. Only the first W
 // entries of each sorted list are stored (rounded up to a lane's entries; W = D stores all).
+// The wavefront's items first .. first + IPW - 1 (of m * LF).
 template <int P, bool VEC, int MODE>
-__global__ __launch_bounds__(256) void hash_query_kernel(
-    const float* __restrict__ V, uint32_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
-    int LF, int D_arg, int W, float* __restrict__ la, uint16_t* __restrict__ lc) {
+__device__ __forceinline__ void hash_wave(
+    uint32_t first, const float* __restrict__ V, uint32_t m, int ldv, int d,
+    const uint32_t* __restrict__ sign_mask, int LF, int D_arg, int W, float* __restrict__ la,
+    uint16_t* __restrict__ lc) {
+  extern __shared__ uint64_t hq_lds[];
   const int D = MODE == kFull ? P : (MODE == kHalf ? P / 2 : D_arg);
   constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI, IPW = QLayout<P>::IPW;
   const int lane = threadIdx.x & 63;
   const int li = lane % LPI;
   const uint32_t items = m * (uint32_t)LF;   // < 2^31 (checked by the launcher)
-  const uint32_t first = (blockIdx.x * 4u + (threadIdx.x >> 6)) * IPW;
-  if (first >= items) return;                // whole wavefront
   const uint32_t item = first + lane / LPI;
   const bool valid = item < items;           // uniform over the item's lanes
   const uint32_t it = valid ? item : 0u;
@@ -400,78 +251,10 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
   const int j0 = li * E;
 
   float v[E];
-  const float* row = V + (size_t)q * ldv;
-  if constexpr (VEC && E % 4 == 0) {
-    // rows are 16-byte aligned: whole float4 groups below d, element loads in the tail group
-#pragma unroll
-    for (int g4 = 0; g4 < E / 4; ++g4) {
-      const int j = j0 + 4 * g4;
-      if (j + 4 <= d) {
-        const float4 x = *reinterpret_cast<const float4*>(row + j);
-        v[4 * g4] = x.x;
-        v[4 * g4 + 1] = x.y;
-        v[4 * g4 + 2] = x.z;
-        v[4 * g4 + 3] = x.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[4 * g4 + e] = (j + e < d) ? row[j + e] : 0.0f;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = (j0 + e < d) ? row[j0 + e] : 0.0f;
-  }
+  load_elems<E, VEC>(V + (size_t)q * ldv, d, j0, v);
   uint32_t smv[3][E];
-  {
-    const uint32_t* sm = sign_mask + (size_t)tf * 3 * P + j0;
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-      if constexpr (E % 4 == 0) {
-#pragma unroll
-        for (int g4 = 0; g4 < E / 4; ++g4) {
-          const uint4 w = *reinterpret_cast<const uint4*>(sm + r * P + 4 * g4);
-          smv[r][4 * g4] = w.x;
-          smv[r][4 * g4 + 1] = w.y;
-          smv[r][4 * g4 + 2] = w.z;
-          smv[r][4 * g4 + 3] = w.w;
-        }
-      } else {
-#pragma unroll
-        for (int e = 0; e < E; ++e) smv[r][e] = sm[r * P + e];
-      }
-    }
-  }
-  // Cross-lane stages use one fused multiply-add: v + w * (+1) in the lower lane of a pair and
-  // v - w (= -(w - v), the same rounding) in the upper one, so an upper lane holds the negated
-  // value. Partners of a later stage differ only in that stage's lane bit, so they carry the
-  // same sign; after a round lane li holds (-1)^popcount(li) times the true values, which the
-  // next round's sign flip and the end of the rotation undo with one XOR of the sign bit. (Only
-  // the sign of a zero can differ, and neither |y| nor the code rule y >= 0 sees it.)
-  const uint32_t lane_sign = (__popc((unsigned)li) & 1) ? 0x80000000u : 0u;
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = flip(v[e], r == 0 ? smv[r][e] : (smv[r][e] ^ lane_sign));
-#pragma unroll
-    for (int h = 1; h < E; h <<= 1) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        if ((e & h) == 0) {
-          const float a = v[e], b = v[e + h];
-          v[e] = a + b;
-          v[e + h] = a - b;
-        }
-      }
-    }
-#pragma unroll
-    for (int hl = 1; hl < LPI; hl <<= 1) {
-      const float mul = (li & hl) ? -1.0f : 1.0f;
-#pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = fmac_xor_n(v[e], hl, mul);
-    }
-  }
-#pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = flip(v[e], lane_sign);
+  load_sign_masks<P, E>(sign_mask, tf, j0, smv);
+  rotate_item<P>(v, smv, li);
   // ---- order the first D outputs by (|y| desc, i asc)
   // 32-bit keys: |y| bits with the low log2(D) bits replaced by D - 1 - i, sorted descending; the
   // order is exact except inside runs of equal truncated |y|, which hold their indices ascending.
@@ -480,7 +263,6 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
   // (a run of three or more) re-sorts the exact keys with the 64-bit network.
   // LDS slot of the item: D floats (the signed outputs by index), reused as D 64-bit keys by the
   // fallback sort
-  extern __shared__ uint64_t hq_lds[];
   uint64_t* slot = hq_lds + (size_t)((threadIdx.x >> 6) * IPW + lane / LPI) * D;
   float* yl = reinterpret_cast<float*>(slot);
   const uint32_t imask = (uint32_t)D - 1u;
@@ -512,6 +294,37 @@ __global__ __launch_bounds__(256) void hash_query_kernel(
     sort_and_store<P / 2, E2, LPI>(k2, li, D, yl, slot, valid, W, ola, olc);
   } else {
     sort_and_store<P, E, LPI>(k32, li, D, yl, slot, valid, W, ola, olc);
+  }
+}
+
+// Wavefront w of the grid takes items w * IPW .. w * IPW + IPW - 1. PICK (the rare vectors that the
+// fused kernel leaves, marked by skip[q] < 0): wavefront w reads the marks of vectors
+// 64 w .. 64 w + 63 at once and computes the lists of the marked ones (and of whatever vectors
+// share their first or last group of IPW items).
+template <int P, bool VEC, int MODE, bool PICK>
+__global__ __launch_bounds__(256) void hash_query_kernel(
+    const float* __restrict__ V, uint32_t m, int ldv, int d, const uint32_t* __restrict__ sign_mask,
+    int LF, int D_arg, int W, float* __restrict__ la, uint16_t* __restrict__ lc,
+    const int32_t* __restrict__ skip) {
+  constexpr int IPW = QLayout<P>::IPW;
+  const uint32_t wv = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if constexpr (!PICK) {
+    const uint32_t first = wv * IPW;
+    if (first < m * (uint32_t)LF)
+      hash_wave<P, VEC, MODE>(first, V, m, ldv, d, sign_mask, LF, D_arg, W, la, lc);
+  } else {
+    const uint32_t q0 = wv * 64u;
+    if (q0 >= m) return;   // whole wavefront
+    const uint32_t qq = q0 + (threadIdx.x & 63);
+    uint64_t marked = __ballot(qq < m && skip[qq] < 0);
+    while (marked) {
+      const uint32_t q = q0 + (uint32_t)__builtin_ctzll(marked);
+      marked &= marked - 1ull;
+      for (uint32_t first = q * (uint32_t)LF; first < (q + 1u) * (uint32_t)LF; first += IPW) {
+        hash_wave<P, VEC, MODE>(first, V, m, ldv, d, sign_mask, LF, D_arg, W, la, lc);
+        wave_lds_sync();   // the next round reuses the wavefront's LDS slots
+      }
+    }
   }
 }
 
@@ -566,7 +379,7 @@ hipError_t launch_hash_build(const fpp_index* ix, int t0, int Tc, uint32_t* rec_
 }
 
 hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int ldv, float* la,
-                             uint16_t* lc, int W, hipStream_t s) {
+                             uint16_t* lc, int W, hipStream_t s, const int32_t* skip) {
   if (m <= 0) return hipSuccess;
   if (W < 1 || W > ix->D) return hipErrorInvalidValue;
   const int LF = ix->L * ix->l;
@@ -575,12 +388,18 @@ hipError_t launch_hash_query(const fpp_index* ix, const float* V, int64_t m, int
   const bool vec = (ix->d % 4 == 0) && (ldv % 4 == 0) && ((uintptr_t)V % 16 == 0);
   const bool full = ix->D == ix->P, half = 2 * ix->D == ix->P;
 #define FPP_HQ_LAUNCH(PP, VV, MM)                                                              \
-  hipLaunchKernelGGL((hash_query_kernel<PP, VV, MM>), grid, dim3(256), lds, s, V, (uint32_t)m,   \
-                     ldv, ix->d, ix->sign_mask, LF, ix->D, W, la, lc)
+  do {                                                                                         \
+    if (skip)                                                                                  \
+      hipLaunchKernelGGL((hash_query_kernel<PP, VV, MM, true>), grid, dim3(256), lds, s, V,     \
+                         (uint32_t)m, ldv, ix->d, ix->sign_mask, LF, ix->D, W, la, lc, skip);    \
+    else                                                                                       \
+      hipLaunchKernelGGL((hash_query_kernel<PP, VV, MM, false>), grid, dim3(256), lds, s, V,    \
+                         (uint32_t)m, ldv, ix->d, ix->sign_mask, LF, ix->D, W, la, lc, skip);    \
+  } while (0)
 #define FPP_HQ(PP)                                                                             \
   case PP: {                                                                                   \
     const int64_t waves = (items + QLayout<PP>::IPW - 1) / QLayout<PP>::IPW;                   \
-    const dim3 grid((unsigned)((waves + 3) / 4));                                              \
+    const dim3 grid((unsigned)(skip ? (m + 255) / 256 : (waves + 3) / 4));                     \
     const size_t lds = (size_t)4 * QLayout<PP>::IPW * ix->D * sizeof(uint64_t);               \
     if (vec && full) {                                                                         \
       FPP_HQ_LAUNCH(PP, true, kFull);                                                          \

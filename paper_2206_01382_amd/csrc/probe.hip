@@ -586,7 +586,8 @@ int probe_list_len(const fpp_index* ix, int32_t qcap) {
 
 hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint16_t* lc, int64_t m,
                                const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
-                               int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s) {
+                               int32_t probe_score, uint32_t* probes, int32_t* nprobe, hipStream_t s,
+                               bool only_unfinished) {
   if (m <= 0) return hipSuccess;
   const int M = probe_prefix(ix, qcap);
   const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + ix->L + 1) * 4;
@@ -597,7 +598,7 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
   }
   // the sparse selection first, where some query may qualify (4 qP <= L); the bisection then
   // takes the queries it left (nprobe = -1)
-  const bool sparse = ix->L <= kRankTables && ix->D % 4 == 0 &&
+  const bool sparse = !only_unfinished && ix->L <= kRankTables && ix->D % 4 == 0 &&
                       (qp_arr != nullptr || 4 * (int64_t)std::min(qp_uniform, qcap) <= ix->L);
   if (sparse)
     hipLaunchKernelGGL(probe_sparse_kernel, dim3((unsigned)m), dim3(kProbeThreads),
@@ -605,7 +606,8 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
                        ix->L, ix->l, ix->D, ix->NB, qp_arr, qp_uniform, qcap, probe_score, probes,
                        nprobe);
   hipLaunchKernelGGL(probe_kernel, dim3((unsigned)m), dim3(kProbeThreads), lds, s, la, lc, m, ix->L,
-                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probe_score, sparse ? 1 : 0,
+                     ix->l, ix->D, M, ix->NB, qp_arr, qp_uniform, qcap, probe_score,
+                     (sparse || only_unfinished) ? 1 : 0,
                      probes, nprobe);
   return hipGetLastError();
 }
