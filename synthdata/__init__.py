@@ -97,6 +97,11 @@ WORKLOADS = {
     "c2_cluster_1m_d128": dict(kind="cluster", n=1_000_000, d=128, m=10_000, centers=1000,
                                spread=0.3, seed=0, L=100, D=128, l=2, alpha=0.3, iProbes=3,
                                k=10, qpt=(10, 20, 50, 100, 200)),
+    # the headline shape with four times the points and clusters (n=4M, 4000 clusters of about
+    # 1000 points): its BF16 store (1 GB) is four times the 256 MB last-level cache of the GPU
+    "c2x4_cluster_4m_d128": dict(kind="cluster", n=4_000_000, d=128, m=10_000, centers=4000,
+                                 spread=0.3, seed=0, L=100, D=128, l=2, alpha=0.3, iProbes=3,
+                                 k=10, qpt=(10, 20, 50, 100, 200)),
     # n=1M, d=300, 2000 clusters, spread 0.4; L=128, D=256 (hash pads d to 512).
     "c3_cluster_1m_d300": dict(kind="cluster", n=1_000_000, d=300, m=10_000, centers=2000,
                                spread=0.4, seed=0, L=128, D=256, l=2, alpha=0.2, iProbes=3,
