@@ -234,6 +234,7 @@ def serving_run(torch, F, h, Qd, *, store, qps_offered, n_queries, k_choices, qp
             row += math.ceil(sizes[i] * ks[i] / kmax)
             qrow += sizes[i]
         arrive_ns = (arrive * 1e9).astype(np.int64)
+        torch.cuda.synchronize()   # the server's streams are not ordered after torch's
         start = time.monotonic_ns() + 2_000_000
         # the native load generator submits each request at its scheduled time
         tickets = F.fpp_server_replay(sv, Qd.data_ptr(), start, arrive_ns, q_row, sizes, ks, qps,

@@ -208,6 +208,9 @@ typedef struct fpp_index_info {
   float threshold;         /* FPP_FILTER_THRESHOLD: the float32 bound on |y| the build
                               compared against (fl32(P * t)); 0 otherwise             */
   int32_t simhash_bits;    /* F * D of the SimHash store (0 if not built)           */
+  int32_t overflow_sets;   /* sets of gather overflow bitmaps allocated so far: a query call
+                              takes one whose last call has finished, else a new one (up to 4),
+                              so calls in flight on different streams do not wait for each other */
 } fpp_index_info;
 
 int fpp_index_get_info(const fpp_index* index, fpp_index_info* info);
@@ -245,8 +248,10 @@ int fpp_server_create(const fpp_index* index, const fpp_server_opts* opts, fpp_s
 
 /*
  * Submit one request: Q device float32 [m][d]; ids_out / scores_out device [m][k].
- * The buffers must stay valid until the request completes. Returns a ticket (> 0) in
- * *ticket. Errors: FPP_EINVAL, FPP_ECAPACITY (the request alone needs more scratch than
+ * The buffers must stay valid until the request completes. The server's streams are not
+ * ordered after any stream of the caller: Q must already hold its values, and no pending work
+ * may write to ids_out / scores_out, when the call is made (synchronise the producing stream
+ * first). Returns a ticket (> 0) in *ticket. Errors: FPP_EINVAL, FPP_ECAPACITY (the request alone needs more scratch than
  * the pool holds), FPP_ESTATE (server stopping).
  */
 int fpp_server_submit(fpp_server* server, const float* Q, int32_t m, int32_t k, int32_t qProbes,

@@ -56,7 +56,8 @@ class fpp_index_info(ctypes.Structure):
                 ("iProbes", c_i32), ("stores", c_i32), ("alpha", c_f32), ("seed", c_u64),
                 ("buckets_per_table", c_i64), ("total_ids", c_i64), ("max_bucket", c_i64),
                 ("device_bytes", c_i64), ("build_ms", ctypes.c_double), ("kappa", c_i32),
-                ("centered", c_i32), ("filter", c_i32), ("threshold", c_f32), ("simhash_bits", c_i32)]
+                ("centered", c_i32), ("filter", c_i32), ("threshold", c_f32), ("simhash_bits", c_i32),
+                ("overflow_sets", c_i32)]
 
 
 class fpp_server_opts(ctypes.Structure):

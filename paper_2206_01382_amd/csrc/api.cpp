@@ -154,10 +154,12 @@ static void free_index_memory(fpp_index* ix) {
                   ix->offsets, ix->ids, ix->center_vec, ix->Xsig};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  if (ix->gbm) (void)hipFree(ix->gbm);
-  if (ix->gbm_free) (void)hipEventDestroy(ix->gbm_free);
-  ix->gbm = nullptr;
-  ix->gbm_free = nullptr;
+  for (int i = 0; i < fpp_index::kGbmSets; ++i) {
+    if (ix->gbm[i]) (void)hipFree(ix->gbm[i]);
+    if (ix->gbm_free[i]) (void)hipEventDestroy(ix->gbm_free[i]);
+    ix->gbm[i] = nullptr;
+    ix->gbm_free[i] = nullptr;
+  }
 }
 
 // Serialises the hand-over of an index's overflow bitmaps between calls (host side only).
@@ -569,26 +571,43 @@ static int query_common(const fpp_index* ix, QuerySpec& qs, hipStream_t s) {
   }
   std::call_once(g_pool_once, configure_pool);
   const Layout ly = plan_layout(ix, qs.m, qs.qp_max, qs.k_max, qs.store, qs.R_opt, (int64_t)4 << 30, false);
-  // the index's overflow bitmaps: this call's stream waits until the previous call is done with
-  // them; the lock is held while this call's kernels are enqueued
+  // a set of overflow bitmaps for this call: one last used on this stream (stream order frees
+  // it), else one whose last user has finished, else a new one, else the one taken longest ago
+  // (this call's stream then waits for its last user)
+  // The lock is held while this call's kernels are enqueued (host side only), so that the set's
+  // event records this call before another call can take the set.
+  int set = -1;
   std::unique_lock<std::mutex> gbm_lock(g_gbm_mu);
-  if (!ix->gbm) {
-    const size_t b = overflow_bitmap_bytes(ix);
-    FPP_HIP(hipMalloc((void**)&ix->gbm, b));
-    const hipError_t e = hipMemset(ix->gbm, 0, b);
-    if (e == hipSuccess) {
-      const hipError_t f = hipEventCreateWithFlags(&ix->gbm_free, hipEventDisableTiming);
-      if (f != hipSuccess) ix->gbm_free = nullptr;
+  {
+    for (int i = 0; i < fpp_index::kGbmSets && set < 0; ++i)
+      if (ix->gbm[i] && ix->gbm_stream[i] == s) set = i;
+    for (int i = 0; i < fpp_index::kGbmSets && set < 0; ++i)
+      if (ix->gbm[i] && hipEventQuery(ix->gbm_free[i]) == hipSuccess) set = i;
+    for (int i = 0; i < fpp_index::kGbmSets && set < 0; ++i) {
+      if (ix->gbm[i]) continue;
+      const size_t b = overflow_bitmap_bytes(ix);
+      FPP_HIP(hipMalloc((void**)&ix->gbm[i], b));
+      hipError_t e = hipMemset(ix->gbm[i], 0, b);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&ix->gbm_free[i], hipEventDisableTiming);
+      if (e != hipSuccess) {
+        (void)hipFree(ix->gbm[i]);
+        ix->gbm[i] = nullptr;
+        ix->gbm_free[i] = nullptr;
+        return hip_fail(e, "overflow bitmaps", __FILE__, __LINE__);
+      }
+      set = i;
     }
-    if (e != hipSuccess || !ix->gbm_free) {
-      (void)hipFree(ix->gbm);
-      ix->gbm = nullptr;
-      return hip_fail(e != hipSuccess ? e : hipErrorOutOfMemory, "overflow bitmaps", __FILE__, __LINE__);
+    if (set < 0) {
+      set = 0;
+      for (int i = 1; i < fpp_index::kGbmSets; ++i)
+        if (ix->gbm_stamp[i] < ix->gbm_stamp[set]) set = i;
     }
-    FPP_HIP(hipEventRecord(ix->gbm_free, s));
+    ix->gbm_stamp[set] = ++ix->gbm_calls;
+    ix->gbm_stream[set] = s;
+    // the set's previous user (if any) finishes before this call's kernels start
+    FPP_HIP(hipStreamWaitEvent(s, ix->gbm_free[set], 0));
+    qs.gbm_ext = ix->gbm[set];
   }
-  FPP_HIP(hipStreamWaitEvent(s, ix->gbm_free, 0));
-  qs.gbm_ext = ix->gbm;
   size_t arr_bytes = 0;
   if (qs.k_host) arr_bytes = a256((size_t)qs.m * 16);
   unsigned char* ws = nullptr;
@@ -618,7 +637,7 @@ static int query_common(const fpp_index* ix, QuerySpec& qs, hipStream_t s) {
     std::vector<hipEvent_t> ev;
     rc = run_queries(ix, qs, ly, ws, s, qs.stage_ms ? &ev : nullptr);
     {
-      const hipError_t e = hipEventRecord(ix->gbm_free, s);
+      const hipError_t e = hipEventRecord(ix->gbm_free[set], s);
       if (rc == FPP_OK && e != hipSuccess) rc = hip_fail(e, "hipEventRecord", __FILE__, __LINE__);
     }
     gbm_lock.unlock();
@@ -775,6 +794,11 @@ int fpp_index_get_info(const fpp_index* ix, fpp_index_info* info) {
   info->filter = ix->filter;
   info->threshold = ix->filter == FPP_FILTER_THRESHOLD ? ix->thr : 0.f;
   info->simhash_bits = ix->sigF * ix->D;
+  {
+    std::lock_guard<std::mutex> lk(g_gbm_mu);
+    info->overflow_sets = 0;
+    for (int i = 0; i < fpp_index::kGbmSets; ++i) info->overflow_sets += ix->gbm[i] ? 1 : 0;
+  }
   return FPP_OK;
 }
 

@@ -74,11 +74,18 @@ struct fpp_index {
   uint32_t* offsets = nullptr;    // device [L][NB + 1], absolute positions into ids
   int32_t* ids = nullptr;         // device [total_ids]
 
-  // Overflow bitmaps of the gather kernel for fpp_query / fpp_query_ex / fpp_query_batch:
-  // allocated zeroed by the first query and kept zero by the kernel; calls take turns on them
-  // through gbm_free (each call's stream waits for the previous call's queries).
-  mutable uint32_t* gbm = nullptr;
-  mutable hipEvent_t gbm_free = nullptr;
+  // Overflow bitmaps and work counters of the gather kernel for fpp_query / fpp_query_ex /
+  // fpp_query_batch: up to kGbmSets sets, each allocated zeroed when a call finds every existing
+  // set still in use, and kept zero by the kernel. A call takes the set last used on its own
+  // stream, else a set whose last user has finished (its event has completed), else allocates
+  // one, else waits (on its stream) for the set used longest ago; so calls on different streams
+  // overlap up to kGbmSets deep, and calls on one stream share one set.
+  static constexpr int kGbmSets = 4;
+  mutable uint32_t* gbm[kGbmSets] = {};
+  mutable hipEvent_t gbm_free[kGbmSets] = {};
+  mutable hipStream_t gbm_stream[kGbmSets] = {};   // stream of the set's last user
+  mutable uint64_t gbm_stamp[kGbmSets] = {};   // call counter when the set was last taken
+  mutable uint64_t gbm_calls = 0;
 
   std::vector<int64_t> table_base;   // host [L + 1]
   int64_t total_ids = 0;

@@ -1,6 +1,6 @@
 // Query hashing and probe selection in one kernel, for probe budgets of up to about two probes per
-// table (Section 3.4, multi-probing for querying; Section 2.2 Eq. 1 for the hash; qProbes is a
-// total over the L tables).
+// table and D = P <= 256 or D = P / 2 <= 128 (Section 3.4, multi-probing for querying; Section 2.2
+// Eq. 1 for the hash; qProbes is a total over the L tables).
 //
 // The selection needs the qProbes best (table, bucket) pairs of a query by the pair score
 // s = fl32(|y1_a| + |y2_b|) (l = 2; s = |y_a| for l = 1), in the order (s desc, table asc,
@@ -93,13 +93,15 @@ __device__ __forceinline__ void qth_largest(const float* v, int n, int q, float*
 
 // One workgroup per query; its threads take the functions in passes of IPB = blockDim.x / LPI
 // (function base + thread / LPI).
-template <int P, bool VEC>
+// HALF: D = P / 2 (the listed outputs are j < D, held by the lower half of an item's lanes), else
+// D = P.
+template <int P, bool VEC, bool HALF>
 __global__ __launch_bounds__(512) void hash_probe_kernel(
     const float* __restrict__ V, int64_t m, int ldv, int d, const uint32_t* __restrict__ sign_bits,
     int L, int l, int64_t NB, const int32_t* __restrict__ qp_arr, int32_t qp_uniform, int32_t qcap,
     uint32_t* __restrict__ probes, int32_t* __restrict__ nprobe) {
   constexpr int E = QLayout<P>::E, LPI = QLayout<P>::LPI;
-  constexpr int D = P;   // this path lists every output (D == P)
+  constexpr int D = HALF ? P / 2 : P;
   const int64_t q = blockIdx.x;
   if (q >= m) return;   // uniform
   const int LF = L * l;
@@ -134,7 +136,7 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
     float m1 = -1.0f, m2 = -1.0f;   // below every |y|
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const float a = fabsf(v[e]);
+      const float a = (!HALF || j0 + e < D) ? fabsf(v[e]) : -1.0f;   // listed outputs only
       m2 = __builtin_amdgcn_fmed3f(m1, m2, a);   // m1 >= m2: the new second best
       m1 = fmaxf(m1, a);
     }
@@ -215,7 +217,7 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
       for (int e = 0; e < E; ++e) {
         const float a = fabsf(v[e]);
         const float s = l == 2 ? a + mo : a;
-        if (s >= mn) {
+        if ((!HALF || j0 + e < D) && s >= mn) {
           const uint32_t x = atomicAdd(&st->ecount, 1u);
           if (x < (uint32_t)kEntCap) {
             ent[x] = pack_entry(item, j0 + e, v[e]);
@@ -345,7 +347,7 @@ int hp_waves(int LF) {
   return best;
 }
 
-template <int P>
+template <int P, bool HALF>
 hipError_t launch_hp_p(const fpp_index* ix, const float* V, int64_t m, int ldv, const int32_t* qp_arr,
                        int32_t qp_uniform, int32_t qcap, uint32_t* probes, int32_t* nprobe,
                        hipStream_t s) {
@@ -354,13 +356,13 @@ hipError_t launch_hp_p(const fpp_index* ix, const float* V, int64_t m, int ldv, 
   const HPLayout lo(LF, ix->L, ix->l);
   const dim3 block(64 * hp_waves<P>(LF));
   if (vec)
-    hipLaunchKernelGGL((hash_probe_kernel<P, true>), dim3((unsigned)m), block, lo.total, s, V, m, ldv,
-                       ix->d, ix->sign_bits, ix->L, ix->l, ix->NB, qp_arr, qp_uniform, qcap, probes,
-                       nprobe);
+    hipLaunchKernelGGL((hash_probe_kernel<P, true, HALF>), dim3((unsigned)m), block, lo.total, s, V,
+                       m, ldv, ix->d, ix->sign_bits, ix->L, ix->l, ix->NB, qp_arr, qp_uniform, qcap,
+                       probes, nprobe);
   else
-    hipLaunchKernelGGL((hash_probe_kernel<P, false>), dim3((unsigned)m), block, lo.total, s, V, m, ldv,
-                       ix->d, ix->sign_bits, ix->L, ix->l, ix->NB, qp_arr, qp_uniform, qcap, probes,
-                       nprobe);
+    hipLaunchKernelGGL((hash_probe_kernel<P, false, HALF>), dim3((unsigned)m), block, lo.total, s, V,
+                       m, ldv, ix->d, ix->sign_bits, ix->L, ix->l, ix->NB, qp_arr, qp_uniform, qcap,
+                       probes, nprobe);
   return hipGetLastError();
 }
 
@@ -368,7 +370,11 @@ hipError_t launch_hp_p(const fpp_index* ix, const float* V, int64_t m, int ldv, 
 
 bool hash_probe_applies(const fpp_index* ix, int32_t qp_max, int32_t probe_score, int32_t store) {
   if (probe_score != FPP_PROBE_SUM || store == FPP_STORE_SIMHASH) return false;
-  if (ix->D != ix->P || ix->P < 16 || ix->P > 256) return false;
+  const bool full = ix->D == ix->P && ix->P >= 16 && ix->P <= 256;
+  // at P = 512 the second rotation of the active tables costs more than the list kernel's sort
+  // saves (measured at d = 300, L = 128, qProbes = 200), so D = P / 2 stops at P = 256
+  const bool half = 2 * ix->D == ix->P && ix->P >= 32 && ix->P <= 256;
+  if (!full && !half) return false;
   if (ix->L > kMaxTables || (ix->l != 1 && ix->l != 2)) return false;
   if ((int64_t)ix->L * ix->D * ix->D >= ((int64_t)1 << 32) || (ix->NB + 1) * (int64_t)ix->L >= ((int64_t)1 << 32))
     return false;
@@ -380,14 +386,28 @@ hipError_t launch_hash_probe(const fpp_index* ix, const float* V, int64_t m, int
                              const int32_t* qp_arr, int32_t qp_uniform, int32_t qcap,
                              uint32_t* probes, int32_t* nprobe, hipStream_t s) {
   if (m <= 0) return hipSuccess;
-  switch (ix->P) {
-    case 16: return launch_hp_p<16>(ix, V, m, ldv, qp_arr, qp_uniform, qcap, probes, nprobe, s);
-    case 32: return launch_hp_p<32>(ix, V, m, ldv, qp_arr, qp_uniform, qcap, probes, nprobe, s);
-    case 64: return launch_hp_p<64>(ix, V, m, ldv, qp_arr, qp_uniform, qcap, probes, nprobe, s);
-    case 128: return launch_hp_p<128>(ix, V, m, ldv, qp_arr, qp_uniform, qcap, probes, nprobe, s);
-    case 256: return launch_hp_p<256>(ix, V, m, ldv, qp_arr, qp_uniform, qcap, probes, nprobe, s);
-    default: return hipErrorInvalidValue;
+#define FPP_HP(PP, HH) return launch_hp_p<PP, HH>(ix, V, m, ldv, qp_arr, qp_uniform, qcap, probes, nprobe, s)
+  if (ix->D == ix->P) {
+    switch (ix->P) {
+      case 16: FPP_HP(16, false);
+      case 32: FPP_HP(32, false);
+      case 64: FPP_HP(64, false);
+      case 128: FPP_HP(128, false);
+      case 256: FPP_HP(256, false);
+      default: return hipErrorInvalidValue;
+    }
   }
+  if (2 * ix->D == ix->P) {
+    switch (ix->P) {
+      case 32: FPP_HP(32, true);
+      case 64: FPP_HP(64, true);
+      case 128: FPP_HP(128, true);
+      case 256: FPP_HP(256, true);
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef FPP_HP
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fpp

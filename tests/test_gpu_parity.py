@@ -384,6 +384,33 @@ def test_concurrent_queries_on_two_streams_share_the_bitmaps():
         assert torch.equal(rb[0], ref_b[0]) and torch.equal(rb[1], ref_b[1])
 
 
+def test_calls_on_two_streams_take_separate_bitmaps():
+    """A call issued on one stream while another call on the same index is still running takes a
+    second set of overflow bitmaps instead of waiting for the first call (the index hands each
+    in-flight call its own set); both results equal the calls made alone."""
+    X, Q = synthdata.clustered_sphere(20_000, 128, 40, 50, 0.3, seed=7)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    h = F().fpp_build_index(Xd, 6, 32, 0.3, 3, SEED, l=2)
+    try:
+        Qbig = Qd.repeat(100, 1).contiguous()   # 4,000 queries with 2,000 probes each: a long call
+        ref_a = F().fpp_query(h, Qbig, 10, 2000)
+        torch.cuda.synchronize()
+        ref_b = F().fpp_query(h, Qd, 10, 48)
+        torch.cuda.synchronize()
+        assert F().fpp_index_get_info(h)["overflow_sets"] == 1   # calls one after another share one
+        sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+        with torch.cuda.stream(sa):
+            ra = F().fpp_query(h, Qbig, 10, 2000, stream=sa)
+        with torch.cuda.stream(sb):
+            rb = F().fpp_query(h, Qd, 10, 48, stream=sb)
+        torch.cuda.synchronize()
+        assert F().fpp_index_get_info(h)["overflow_sets"] == 2
+        assert torch.equal(ra[0], ref_a[0]) and torch.equal(ra[1], ref_a[1])
+        assert torch.equal(rb[0], ref_b[0]) and torch.equal(rb[1], ref_b[1])
+    finally:
+        F().fpp_free_index(h)
+
+
 def test_query_c1_published_qprobes():
     """The small workload as specified: k = 10, 4 probes per table (40 in total), and the
     literal total of 4."""

@@ -49,14 +49,15 @@ def _requests(rng, m_total, n_req, ks, qps):
 
 
 def _run(F, sv, Qd, reqs, kmax, pace_s=0.0):
-    outs = []
+    # the server's streams are not ordered after torch's: the sentinel fills must be done before
+    # the first submission, or a late fill could overwrite a served result
+    outs = [(torch.full((m, k), -7, dtype=torch.int32, device="cuda"),
+             torch.full((m, k), 7.0, dtype=torch.float32, device="cuda")) for (_, m, k, _) in reqs]
+    torch.cuda.synchronize()
     tickets = []
-    for (row, m, k, qp) in reqs:
-        ids = torch.full((m, k), -7, dtype=torch.int32, device="cuda")
-        sc = torch.full((m, k), 7.0, dtype=torch.float32, device="cuda")
+    for (row, m, k, qp), (ids, sc) in zip(reqs, outs):
         q = Qd[row:row + m]
         tickets.append(F.fpp_server_submit(sv, q.data_ptr(), m, k, qp, ids.data_ptr(), sc.data_ptr()))
-        outs.append((ids, sc))
         if pace_s:
             time.sleep(pace_s)
     stamps = [F.fpp_server_wait(sv, t, 60_000) for t in tickets]
@@ -199,6 +200,7 @@ def test_replay_submits_on_schedule_and_matches_direct_queries(env):
     total = int((m.astype(np.int64) * k).sum())
     ids = torch.full((total,), -7, dtype=torch.int32, device="cuda")
     sc = torch.full((total,), 7.0, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()   # the server's streams are not ordered after torch's
     arrive = np.cumsum(rng.exponential(100_000, size=n)).astype(np.int64)   # ~0.1 ms apart
     sv = F.fpp_server_create(h, scratch_bytes=256 << 20, n_streams=2, max_batch=64)
     try:
@@ -231,6 +233,7 @@ def test_failed_batch_fails_only_its_requests(env):
     try:
         ids = torch.full((3, 10), -7, dtype=torch.int32, device="cuda")
         sc = torch.full((3, 10), 7.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
         F.fpp_server_debug_fail_batches(sv, 1)
         t = F.fpp_server_submit(sv, Qd.data_ptr(), 3, 10, 40, ids.data_ptr(), sc.data_ptr())
         st, ts, td = F.fpp_server_wait(sv, t, 60_000)
