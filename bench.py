@@ -478,7 +478,8 @@ def run_secondary(args, name):
         res[store] = {"qps": round(Qd.shape[0] / (ms / 1e3), 1), "ms_per_call": round(ms, 3),
                       "median_ms": round(med, 3), "stage_ms": [round(x, 4) for x in stage],
                       "gather_gbs": round(byt / (stage[2] / 1e3) / 1e9, 1),
-                      "unique_per_query": float(st[:, 2].mean())}
+                      "unique_per_query": float(st[:, 2].mean()),
+                      "entries_per_query": float(st[:, 1].mean())}
         log(f"{store}: {ms:.3f} ms per {Qd.shape[0]} queries; stages {stage.round(3)} gather {res[store]['gather_gbs']} GB/s")
     sharing = None
     if not name.startswith("c5"):

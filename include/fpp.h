@@ -341,6 +341,15 @@ int fpp_debug_center(const fpp_index* index, float* c_out);
 int fpp_debug_export_store(const fpp_index* index, int32_t store, void* codes_out,
                            float* scales_out, void* stream);
 
+/* For tests of the gather's dedup (Section 4: candidates are deduplicated, each scored once):
+ * queries of this index with more than min_entries probed entries, and no more than n / 32,
+ * are deduplicated by id range (ids grouped by id >> range_bits, each group against an on-chip
+ * bitmap of 2^range_bits bits; at most 256 groups) instead of the on-chip set that spills into
+ * a device bitmap. Both give the same results. min_entries < 0 restores the default (16,384),
+ * range_bits < 0 the default (18); otherwise range_bits must lie in [5, 18]. Not thread-safe
+ * against running queries on the index. Errors: FPP_EINVAL. */
+int fpp_debug_set_partition_threshold(fpp_index* index, int64_t min_entries, int32_t range_bits);
+
 #ifdef __cplusplus
 }
 #endif

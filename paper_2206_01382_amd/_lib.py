@@ -105,6 +105,7 @@ SIGNATURES = {
     "fpp_debug_probes": (c_i32, [c_vp, c_vp, c_i64, c_i32, c_i32, c_vp, c_vp]),
     "fpp_debug_export_store": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "fpp_debug_center": (c_i32, [c_vp, c_vp]),
+    "fpp_debug_set_partition_threshold": (c_i32, [c_vp, c_i64, c_i32]),
     "fpp_normal_quantile": (ctypes.c_double, [ctypes.c_double]),
 }
 
@@ -304,6 +305,12 @@ def fpp_debug_center(h) -> np.ndarray:
     c = np.zeros(inf["d"], dtype=np.float32)
     _check(lib().fpp_debug_center(h, c.ctypes.data_as(c_vp)))
     return c
+
+
+def fpp_debug_set_partition_threshold(h, min_entries: int, range_bits: int = -1) -> None:
+    """Queries with more probed entries than min_entries are deduplicated by id range, in ranges
+    of 2^range_bits ids (< 0: the defaults)."""
+    _check(lib().fpp_debug_set_partition_threshold(h, int(min_entries), int(range_bits)))
 
 
 def fpp_normal_quantile(p: float) -> float:

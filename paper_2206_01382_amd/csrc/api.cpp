@@ -268,7 +268,27 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
   ix->NB = o.l == 1 ? 2LL * D : 4LL * D * D;
   ix->ldx = (d + 3) / 4 * 4;
   ix->ld16 = (d + 7) / 8 * 8;
-  ix->ld8 = (d + 15) / 16 * 16;
+  {
+    // FP8 rows: the codes padded to 16 bytes; where that leaves room in the row's last 128-byte
+    // line, the row's scale follows in a 16-byte chunk of its own and rows are laid out so that
+    // none straddles more lines than its bytes need (a power of two up to 128 bytes, else whole
+    // lines): the gather then fetches a row and its scale together
+    const int codes = (d + 15) / 16 * 16;
+    if (codes % 128 == 0) {
+      ix->ld8 = codes;
+      ix->fp8_sc_off = -1;
+    } else {
+      const int need = codes + 16;
+      int ld = 16;
+      if (need <= 128) {
+        while (ld < need) ld <<= 1;
+      } else {
+        ld = (need + 127) / 128 * 128;
+      }
+      ix->ld8 = ld;
+      ix->fp8_sc_off = codes;
+    }
+  }
   const int64_t NB = ix->NB;
   const int K = iProbes;
   const int64_t nK = n * K;
@@ -876,6 +896,15 @@ int fpp_debug_center(const fpp_index* ix, float* c_out) {
 }
 
 double fpp_normal_quantile(double p) { return normal_quantile(p); }
+
+int fpp_debug_set_partition_threshold(fpp_index* ix, int64_t min_entries, int32_t range_bits) {
+  if (!ix) return set_error("index is NULL"), FPP_EINVAL;
+  if (range_bits >= 0 && (range_bits < 5 || range_bits > fpp_index::kPartShiftDefault))
+    return set_error("range_bits=%d out of [5, %d]", range_bits, fpp_index::kPartShiftDefault), FPP_EINVAL;
+  ix->part_min = min_entries < 0 ? fpp_index::kPartMinDefault : min_entries;
+  ix->part_shift = range_bits < 0 ? fpp_index::kPartShiftDefault : range_bits;
+  return FPP_OK;
+}
 
 int fpp_debug_export_table(const fpp_index* ix, int32_t t, uint32_t* offsets_out, int32_t* ids_out) {
   if (!ix || !offsets_out || !ids_out) return set_error("NULL argument"), FPP_EINVAL;

@@ -57,6 +57,7 @@ struct fpp_index {
   int32_t ldx = 0;           // FP32 row stride in floats (multiple of 4)
   int32_t ld16 = 0;          // BF16 row stride in elements (multiple of 8)
   int32_t ld8 = 0;           // FP8 row stride in bytes (multiple of 16)
+  int32_t fp8_sc_off = -1;   // byte offset of the row's scale inside an FP8 row, or -1 (separate)
   int device = 0;
 
   float* X = nullptr;             // device [n][ldx]
@@ -80,6 +81,11 @@ struct fpp_index {
   // stream, else a set whose last user has finished (its event has completed), else allocates
   // one, else waits (on its stream) for the set used longest ago; so calls on different streams
   // overlap up to kGbmSets deep, and calls on one stream share one set.
+  // the gather deduplicates a query by id range when it has more probed entries than this
+  int64_t part_min = kPartMinDefault;
+  int32_t part_shift = kPartShiftDefault;   // ids per range: 2^part_shift (at most 2^18)
+  static constexpr int64_t kPartMinDefault = 16384;
+  static constexpr int32_t kPartShiftDefault = 18;
   static constexpr int kGbmSets = 4;
   mutable uint32_t* gbm[kGbmSets] = {};
   mutable hipEvent_t gbm_free[kGbmSets] = {};

@@ -3,7 +3,8 @@
 //   FP8:  per vector s = fl32(max|x| / 448) (s = 1 for a zero vector); element codes are
 //         OCP E4M3 (bias 7, largest finite 448, no infinities) of fl32(x / s), nearest with
 //         ties to the even code, magnitudes >= 448 saturating to 448.
-// Rows are padded with zeros to a multiple of 16 bytes.
+// Rows are padded with zeros to a multiple of 16 bytes; an FP8 row may also carry its scale
+// (after the codes, in a 16-byte chunk of its own).
 #include "fpp_internal.hpp"
 
 namespace fpp {
@@ -47,10 +48,10 @@ __global__ __launch_bounds__(256) void quant_bf16_kernel(const float* __restrict
   out[i] = c < d ? bf16_rne(X[r * ldx + c]) : (uint16_t)0;
 }
 
-// One wavefront per row.
+// One wavefront per row. With sc_off >= 0 the scale is also stored inside the row at byte sc_off.
 __global__ __launch_bounds__(256) void quant_fp8_kernel(const float* __restrict__ X, int64_t n,
                                                         int d, int ldx, uint8_t* __restrict__ out,
-                                                        int ld8, float* __restrict__ scale) {
+                                                        int ld8, int sc_off, float* __restrict__ scale) {
   const int lane = threadIdx.x & 63;
   const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (r >= n) return;
@@ -61,8 +62,12 @@ __global__ __launch_bounds__(256) void quant_fp8_kernel(const float* __restrict_
   for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
   const float s = mx == 0.0f ? 1.0f : __fdiv_rn(mx, 448.0f);
   for (int c = lane; c < ld8; c += 64)
-    out[r * ld8 + c] = c < d ? (uint8_t)e4m3_rne_sat(__fdiv_rn(x[c], s)) : (uint8_t)0;
-  if (lane == 0) scale[r] = s;
+    if (sc_off < 0 || c < sc_off || c >= sc_off + 4)
+      out[r * ld8 + c] = c < d ? (uint8_t)e4m3_rne_sat(__fdiv_rn(x[c], s)) : (uint8_t)0;
+  if (lane == 0) {
+    scale[r] = s;
+    if (sc_off >= 0) *reinterpret_cast<float*>(out + r * ld8 + sc_off) = s;
+  }
 }
 
 // Centred copy for the build's hashing: xc[i][j] = fl32(x[i][j] - c[j]) for j < d, 0 in the row
@@ -93,7 +98,7 @@ hipError_t launch_quantize(const fpp_index* ix, hipStream_t s) {
   }
   if (ix->Xfp8) {
     hipLaunchKernelGGL(quant_fp8_kernel, dim3((unsigned)((ix->n + 3) / 4)), dim3(256), 0, s, ix->X,
-                       ix->n, ix->d, ix->ldx, ix->Xfp8, ix->ld8, ix->fp8_scale);
+                       ix->n, ix->d, ix->ldx, ix->Xfp8, ix->ld8, ix->fp8_sc_off, ix->fp8_scale);
   }
   return hipGetLastError();
 }

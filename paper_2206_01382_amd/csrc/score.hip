@@ -7,7 +7,10 @@
 //      consecutive entries, reads their ids and inserts them into an LDS open-addressing set
 //      (set semantics: an id is scored once however many buckets hold it). Past 3072 distinct
 //      ids the workgroup moves the set into its n-bit bitmap in device memory and continues
-//      there. First-time ids enter an LDS queue.
+//      there. First-time ids enter an LDS queue. A query with more than 16,384 entries (by
+//      default; they must fit the workgroup's bitmap region as a buffer) is deduplicated by id range instead: its
+//      ids are grouped by id >> 18 into that buffer and each group is tested against an LDS
+//      bitmap of its 2^18 ids.
 //   B. when the queue holds >= 1024 ids (and at the end) the waves score it: G lanes cover one
 //      row with 16-byte loads, each lane folds its chunks into a float32 partial in a fixed order,
 //      and a fixed xor-shuffle tree over the G lanes finishes the sum. Scores therefore do not
@@ -35,7 +38,12 @@ constexpr int kProbeChunk = kBlock;
 constexpr int kSetSlots = 8192;                 // LDS id set (open addressing), 2^13 slots
 constexpr int kSetLimit = kSetSlots / 2 - kRound;   // switch to the bitmap above this many ids
 constexpr uint32_t kEmpty = 0xffffffffu;
-constexpr int kBlocksPerCU = 3;                 // ~50 KB of LDS per workgroup
+constexpr int kBlocksPerCU = 3;                 // ~51 KB of LDS per workgroup
+// partitioned dedup (queries with many probed entries): ids are grouped by id >> shift, and each
+// group is deduplicated in a bitmap over its 2^shift ids that occupies the set's LDS
+constexpr int kMaxPartShift = 18;               // 2^18 bits = kSetSlots words
+constexpr int kMaxParts = kBlock;               // id ranges, one count per thread
+static_assert((1 << kMaxPartShift) == kSetSlots * 32, "a range's bitmap fits the set's LDS");
 
 template <int STORE>
 struct Elems;
@@ -297,7 +305,8 @@ struct ScoreParams {
   uint32_t ld_bytes;         // store row stride in bytes (at most 4 KB: the offset of a row is
                              // one 32 x 32 -> 64-bit multiply-add)
   int nchunks;               // 16-byte chunks per stored row
-  const float* scale;        // FP8 per-row scales
+  const unsigned char* sc_base;   // FP8 per-row scale of row i at sc_base + i * sc_stride
+  uint32_t sc_stride;
   const uint32_t* offsets;
   const int32_t* ids;
   int64_t n;
@@ -322,6 +331,8 @@ struct ScoreParams {
   uint32_t* work;            // [2]: next query, finished workgroups; zero on entry and on exit
   const unsigned char* zero16;   // 16 bytes that stay zero (after the work counters)
   int64_t bm_words;
+  int64_t part_min;          // more probed entries than this: dedup by id range
+  int32_t part_shift;        // ids per range: 2^part_shift <= 2^kMaxPartShift
   float sig_bits;            // SimHash: bits per signature
 };
 
@@ -341,7 +352,8 @@ constexpr size_t kOffSet = kOffCand + (size_t)kCandCap * 8;
 constexpr size_t kOffQueue = kOffSet + (size_t)kSetSlots * 4;
 constexpr size_t kOffBeg = kOffQueue + (size_t)kQueueCap * 4;
 constexpr size_t kOffPre = kOffBeg + (size_t)kProbeChunk * 4;
-constexpr size_t kOffWsum = kOffPre + (size_t)(kProbeChunk + 1) * 4;
+constexpr size_t kOffPart = kOffPre + (size_t)(kProbeChunk + 1) * 4;
+constexpr size_t kOffWsum = kOffPart + (size_t)kMaxParts * 4;
 constexpr size_t kOffState = align_up(kOffWsum + (size_t)(kWaves + 2) * 4, 8);
 constexpr size_t kLdsBytes = align_up(kOffState + sizeof(SharedState), 16);
 
@@ -379,6 +391,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
   uint32_t* queue = reinterpret_cast<uint32_t*>(smem + kOffQueue);
   uint32_t* s_beg = reinterpret_cast<uint32_t*>(smem + kOffBeg);
   uint32_t* s_pre = reinterpret_cast<uint32_t*>(smem + kOffPre);
+  uint32_t* s_part = reinterpret_cast<uint32_t*>(smem + kOffPart);
   uint32_t* wsum = reinterpret_cast<uint32_t*>(smem + kOffWsum);
   SharedState* st = reinterpret_cast<SharedState*>(smem + kOffState);
   uint32_t* bitmap = p.gbitmap + (size_t)blockIdx.x * p.bm_words;
@@ -436,7 +449,9 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     auto load_pass = [&](uint32_t rbase, uint32_t rows, uint4 (&w)[U][C], float& scl) {
       if constexpr (STORE == FPP_STORE_FP8) {
         const uint32_t myrow = rbase + (uint32_t)reduced_row<G, U>(g) * RPI + sub;
-        scl = p.scale[queue[myrow < rows ? myrow : rows - 1]];
+        // (inside the row itself when the store keeps it there: the same line as the codes)
+        scl = *reinterpret_cast<const float*>(
+            p.sc_base + (uint64_t)queue[myrow < rows ? myrow : rows - 1] * p.sc_stride);
       }
       uint32_t rid[U];
 #pragma unroll
@@ -516,105 +531,216 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     // ---- A: gather + dedup, flushing the queue into B whenever it fills
     const int32_t np = p.nprobe[q];
     const uint32_t* pr = p.probes + (size_t)q * p.qcap;
+
+    // CSR ranges of probes [c, c + nc) into s_beg / s_pre (exclusive prefix of the lengths);
+    // returns the chunk's entry count
+    auto scan_chunk = [&](int32_t c, int nc) -> uint32_t {
+      uint32_t beg = 0, len = 0;
+      if (tid < nc) {
+        const uint32_t gb = pr[c + tid];
+        beg = p.offsets[gb];
+        len = p.offsets[gb + 1] - beg;
+      }
+      uint32_t ec;
+      const uint32_t pre = block_excl_scan(len, ec, wsum);
+      s_beg[tid] = beg;
+      s_pre[tid] = pre;
+      if (tid == 0) s_pre[kProbeChunk] = ec;
+      __syncthreads();
+      return ec;
+    };
+    // the ids of entries [e, e + kEPT) of the scanned chunk (-1 past its end): one search, then a
+    // linear walk over the probes
+    auto load_entries = [&](uint32_t e, uint32_t ec, int nc, int32_t (&idv)[kEPT]) {
+#pragma unroll
+      for (int u = 0; u < kEPT; ++u) idv[u] = -1;
+      if (e < ec) {
+        int lo = 0, hi = nc;   // s_pre[lo] <= e < s_pre[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+#pragma unroll
+        for (int u = 0; u < kEPT; ++u) {
+          const uint32_t eu = e + u;
+          if (eu < ec) {
+            while (s_pre[lo + 1] <= eu) ++lo;
+            idv[u] = p.ids[s_beg[lo] + (eu - s_pre[lo])];
+          }
+        }
+      }
+    };
+    // queue the first occurrences (bit u of `fresh`) in lane-major order: one ballot per entry
+    // slot gives every lane the count of fresh entries of the lanes below it
+    auto enqueue = [&](const int32_t (&idv)[kEPT], uint32_t fresh) {
+      const uint64_t below = (1ull << lane) - 1ull;
+      uint32_t before = 0, wtot = 0;
+#pragma unroll
+      for (int u = 0; u < kEPT; ++u) {
+        const uint64_t mk = __ballot((fresh >> u) & 1u);
+        before += (uint32_t)__popcll(mk & below);
+        wtot += (uint32_t)__popcll(mk);
+      }
+      uint32_t basepos = 0;
+      if (lane == 0 && wtot) {
+        basepos = atomicAdd(&st->qcount, wtot);
+        atomicAdd(&st->uniq, wtot);
+      }
+      basepos = __builtin_amdgcn_readfirstlane(basepos);
+      uint32_t pos = basepos + before;
+#pragma unroll
+      for (int u = 0; u < kEPT; ++u)
+        if (fresh & (1u << u)) queue[pos++] = (uint32_t)idv[u];
+      __syncthreads();
+    };
+
+    // entry count: the first chunk's scan, or (more than one chunk) a pass over all the ranges
     uint64_t entries = 0;
     int32_t pc = 0;      // next probe chunk
     int npc = 0;         // probes in the current chunk
     uint32_t ec = 0;     // entries of the current chunk
-    uint32_t e0 = 0;     // next entry of the current chunk
-    for (;;) {
-      bool exhausted = false;
-      while (st->qcount < (uint32_t)kQueueFlush) {
-        if (e0 >= ec) {
-          if (pc >= np) {
-            exhausted = true;
-            break;
-          }
-          npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
-          uint32_t beg = 0, len = 0;
-          if (tid < npc) {
-            const uint32_t gb = pr[pc + tid];
-            beg = p.offsets[gb];
-            len = p.offsets[gb + 1] - beg;
-          }
-          const uint32_t pre = block_excl_scan(len, ec, wsum);
-          s_beg[tid] = beg;
-          s_pre[tid] = pre;
-          if (tid == 0) s_pre[kProbeChunk] = ec;
-          __syncthreads();
-          entries += ec;
-          pc += kProbeChunk;
-          e0 = 0;
-          continue;
+    if (np > 0 && np <= kProbeChunk) {
+      npc = np;
+      ec = scan_chunk(0, npc);
+      entries = ec;
+      pc = kProbeChunk;
+    } else if (np > kProbeChunk) {
+      for (int32_t c = 0; c < np; c += kProbeChunk) {
+        const int nc = np - c < kProbeChunk ? np - c : kProbeChunk;
+        uint32_t len = 0;
+        if (tid < nc) {
+          const uint32_t gb = pr[c + tid];
+          len = p.offsets[gb + 1] - p.offsets[gb];
         }
-        const bool ovf = st->overflow != 0;
-        // four consecutive entries per thread: one search, then a linear walk over the probes
-        const uint32_t e = e0 + (uint32_t)tid * kEPT;
-        int32_t idv[kEPT];
+        uint32_t tot;
+        (void)block_excl_scan(len, tot, wsum);
+        entries += tot;
+      }
+    }
+    const int pshift = p.part_shift;
+    const int64_t nparts = (p.n + ((int64_t)1 << pshift) - 1) >> pshift;
+    const bool partitioned = (int64_t)entries > p.part_min && entries <= (uint64_t)p.bm_words &&
+                             nparts <= (int64_t)kMaxParts;
+
+    if (partitioned) {
+      // ---- A': many entries. Pass 1 counts the entries of each id range, pass 2 writes their ids
+      // range by range into the workgroup's bitmap region (used as a buffer: it holds at least
+      // `entries` words), pass 3 deduplicates each range in an LDS bitmap over its 2^pshift ids
+      // (the set's memory) and queues the first occurrences. Three reads of the probed ids
+      // and one write of them replace one device atomic per entry and the clearing of an n-bit
+      // bitmap.
+      uint32_t* buf = bitmap;
+      const uint32_t E = (uint32_t)entries;
+      static_assert(kMaxParts == kBlock, "one range count per thread");
+      s_part[tid] = 0u;
+      __syncthreads();
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int32_t c = 0; c < np; c += kProbeChunk) {
+          const int nc = np - c < kProbeChunk ? np - c : kProbeChunk;
+          const uint32_t ecc = scan_chunk(c, nc);
+          for (uint32_t r = 0; r < ecc; r += kRound) {
+            int32_t idv[kEPT];
+            load_entries(r + (uint32_t)tid * kEPT, ecc, nc, idv);
 #pragma unroll
-        for (int u = 0; u < kEPT; ++u) idv[u] = -1;
-        if (e < ec) {
-          int lo = 0, hi = npc;   // s_pre[lo] <= e < s_pre[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= e) lo = mid;
-            else hi = mid;
-          }
-#pragma unroll
-          for (int u = 0; u < kEPT; ++u) {
-            const uint32_t eu = e + u;
-            if (eu < ec) {
-              while (s_pre[lo + 1] <= eu) ++lo;
-              idv[u] = p.ids[s_beg[lo] + (eu - s_pre[lo])];
+            for (int u = 0; u < kEPT; ++u) {
+              if (idv[u] >= 0) {
+                const uint32_t pi = (uint32_t)idv[u] >> pshift;
+                const uint32_t at = atomicAdd(&s_part[pi], 1u);
+                if (pass == 1) buf[at] = (uint32_t)idv[u];
+              }
             }
           }
         }
-        e0 += kRound;
-        uint32_t fresh = 0;   // bit u: entry u is a first occurrence
-#pragma unroll
-        for (int u = 0; u < kEPT; ++u) {
-          if (idv[u] >= 0) {
-            const bool f = ovf ? bitmap_insert(bitmap, (uint32_t)idv[u]) : set_insert(set, (uint32_t)idv[u]);
-            fresh |= f ? (1u << u) : 0u;
-          }
-        }
-        // enqueue first occurrences in lane-major order: one ballot per entry slot gives every
-        // lane the count of fresh entries of the lanes below it
-        const uint64_t below = (1ull << lane) - 1ull;
-        uint32_t before = 0, wtot = 0;
-#pragma unroll
-        for (int u = 0; u < kEPT; ++u) {
-          const uint64_t mk = __ballot((fresh >> u) & 1u);
-          before += (uint32_t)__popcll(mk & below);
-          wtot += (uint32_t)__popcll(mk);
-        }
-        uint32_t basepos = 0;
-        if (lane == 0 && wtot) {
-          basepos = atomicAdd(&st->qcount, wtot);
-          atomicAdd(&st->uniq, wtot);
-        }
-        basepos = __builtin_amdgcn_readfirstlane(basepos);
-        uint32_t pos = basepos + before;
-#pragma unroll
-        for (int u = 0; u < kEPT; ++u)
-          if (fresh & (1u << u)) queue[pos++] = (uint32_t)idv[u];
         __syncthreads();
-        if (!st->overflow && st->uniq > (uint32_t)kSetLimit) {
-          // move the set into the device bitmap; later entries are tested there
-          for (int i = tid; i < kSetSlots; i += kBlock) {
-            const uint32_t v = set[i];
-            if (v != kEmpty) {
-              atomicOr(&bitmap[v >> 5], 1u << (v & 31));
-              set[i] = kEmpty;
-            }
-          }
-          __threadfence_block();
-          __syncthreads();
-          if (tid == 0) st->overflow = 1;
+        if (pass == 0) {
+          // counts -> first position of each range; after pass 2 s_part[i] is the end of range i
+          const uint32_t v = s_part[tid];
+          uint32_t tot;
+          const uint32_t ex = block_excl_scan(v, tot, wsum);
+          s_part[tid] = ex;
           __syncthreads();
         }
       }
-      score_queue(exhausted);
-      if (exhausted) break;
+      uint32_t* bm = set;
+      for (int i = tid; i < kSetSlots; i += kBlock) bm[i] = 0u;
+      __syncthreads();
+      const uint32_t kLow = (1u << pshift) - 1u;
+      for (int pi = 0; pi < (int)nparts; ++pi) {
+        const uint32_t beg = pi ? s_part[pi - 1] : 0u, end = s_part[pi];
+        for (uint32_t r = beg; r < end; r += kRound) {
+          int32_t idv[kEPT];
+          uint32_t fresh = 0;
+#pragma unroll
+          for (int u = 0; u < kEPT; ++u) {
+            const uint32_t e = r + (uint32_t)tid * kEPT + u;
+            idv[u] = e < end ? (int32_t)buf[e] : -1;
+          }
+#pragma unroll
+          for (int u = 0; u < kEPT; ++u) {
+            if (idv[u] >= 0) {
+              const uint32_t b = (uint32_t)idv[u] & kLow, m = 1u << (b & 31u);
+              fresh |= (atomicOr(&bm[b >> 5], m) & m) ? 0u : (1u << u);
+            }
+          }
+          enqueue(idv, fresh);
+          if (st->qcount >= (uint32_t)kQueueFlush) score_queue(false);
+        }
+        // clear the words of this range's ids
+        for (uint32_t e = beg + tid; e < end; e += kBlock) bm[(buf[e] & kLow) >> 5] = 0u;
+        __syncthreads();
+      }
+      score_queue(true);
+      // the buffer returns to zero (it is the bitmap region), the set's memory to empty slots
+      for (uint32_t e = tid; e < E; e += kBlock) buf[e] = 0u;
+      __threadfence();
+    } else {
+      uint32_t e0 = 0;     // next entry of the current chunk
+      for (;;) {
+        bool exhausted = false;
+        while (st->qcount < (uint32_t)kQueueFlush) {
+          if (e0 >= ec) {
+            if (pc >= np) {
+              exhausted = true;
+              break;
+            }
+            npc = np - pc < kProbeChunk ? np - pc : kProbeChunk;
+            ec = scan_chunk(pc, npc);   // (entries were counted above)
+            pc += kProbeChunk;
+            e0 = 0;
+            continue;
+          }
+          const bool ovf = st->overflow != 0;
+          int32_t idv[kEPT];
+          load_entries(e0 + (uint32_t)tid * kEPT, ec, npc, idv);
+          e0 += kRound;
+          uint32_t fresh = 0;   // bit u: entry u is a first occurrence
+#pragma unroll
+          for (int u = 0; u < kEPT; ++u) {
+            if (idv[u] >= 0) {
+              const bool f = ovf ? bitmap_insert(bitmap, (uint32_t)idv[u]) : set_insert(set, (uint32_t)idv[u]);
+              fresh |= f ? (1u << u) : 0u;
+            }
+          }
+          enqueue(idv, fresh);
+          if (!st->overflow && st->uniq > (uint32_t)kSetLimit) {
+            // move the set into the device bitmap; later entries are tested there
+            for (int i = tid; i < kSetSlots; i += kBlock) {
+              const uint32_t v = set[i];
+              if (v != kEmpty) {
+                atomicOr(&bitmap[v >> 5], 1u << (v & 31));
+                set[i] = kEmpty;
+              }
+            }
+            __threadfence_block();
+            __syncthreads();
+            if (tid == 0) st->overflow = 1;
+            __syncthreads();
+          }
+        }
+        score_queue(exhausted);
+        if (exhausted) break;
+      }
     }
 
     // ---- C: output (the candidates are sorted)
@@ -773,6 +899,8 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.stats = a.stats;
   sp.gbitmap = a.gbitmap;
   sp.bm_words = overflow_bitmap_words(ix);
+  sp.part_min = ix->part_min;
+  sp.part_shift = ix->part_shift;
   sp.work = a.gbitmap + (size_t)a.grid * (size_t)sp.bm_words;   // after the bitmaps
   sp.zero16 = reinterpret_cast<const unsigned char*>(sp.work + 4);   // never written
   sp.short_ids = a.short_ids;
@@ -794,8 +922,14 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
     case FPP_STORE_FP8:
       sp.Xs = reinterpret_cast<const unsigned char*>(ix->Xfp8);
       sp.ld_bytes = (uint32_t)ix->ld8;
-      sp.nchunks = ix->ld8 / 16;
-      sp.scale = ix->fp8_scale;
+      sp.nchunks = (ix->d + 15) / 16;   // code chunks only
+      if (ix->fp8_sc_off >= 0) {
+        sp.sc_base = reinterpret_cast<const unsigned char*>(ix->Xfp8) + ix->fp8_sc_off;
+        sp.sc_stride = (uint32_t)ix->ld8;
+      } else {
+        sp.sc_base = reinterpret_cast<const unsigned char*>(ix->fp8_scale);
+        sp.sc_stride = 4u;
+      }
       return dispatch_store<FPP_STORE_FP8>(sp, grid, s);
     case FPP_STORE_SIMHASH:
       // the query rows (a.Q, a.ldq) are signature words; F * D <= 1024 bits: 8 chunks at most

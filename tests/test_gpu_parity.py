@@ -360,6 +360,34 @@ def test_query_many_candidates_uses_bitmap_dedup(qp):
     assert torch.equal(ids, ids2) and torch.equal(sc, sc2)
 
 
+@pytest.mark.parametrize("name,qp,bits", [("c1_gauss_10k_d64", 8, 8), ("l2_clustered", 16, 8),
+                                           ("l2_clustered", 40, 7), ("pad_d100_D16", 4, 5),
+                                           ("manyL_d24_L40", 2, 5), ("odd_d30_D32", 4, 5)])
+def test_partitioned_dedup_matches_oracle(name, qp, bits):
+    """Queries deduplicated by id range (forced for every query whose probed entries fit the
+    workgroup's buffer of n / 32 ids, in ranges of 2^bits ids) give the oracle's candidate counts
+    and top-k (Section 4: each candidate is scored once), and the same ids and scores as the
+    on-chip set, on the FP32 and the BF16 + rerank paths."""
+    w, oi, h, Xd, Qd = built(name)
+    n = w["X"].shape[0]
+    bm_words = ((n + 31) // 32 + 3) & ~3
+    ref = {st: F().fpp_query(h, Qd, 10, qp, store=st) for st in ("fp32", "bf16")}
+    F().fpp_debug_set_partition_threshold(h, 0, bits)
+    try:
+        ids, sc, st = F().fpp_query(h, Qd, 10, qp, stats=True)
+        low = F().fpp_query(h, Qd, 10, qp, store="bf16")
+    finally:
+        F().fpp_debug_set_partition_threshold(h, -1, -1)
+    st = st.cpu().numpy()
+    assert ((st[:, 1] > 0) & (st[:, 1] <= bm_words)).sum() >= 3   # queries that took the path
+    oids, osc, ost = O.query(oi, w["Q"], 10, qp)
+    np.testing.assert_array_equal(st, ost)
+    swaps = check_topk(w["X"], w["Q"], ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+    assert swaps <= swap_budget(ids.numel()), swaps
+    assert torch.equal(ids, ref["fp32"][0]) and torch.equal(sc, ref["fp32"][1])
+    assert torch.equal(low[0], ref["bf16"][0]) and torch.equal(low[1], ref["bf16"][1])
+
+
 def test_concurrent_queries_on_two_streams_share_the_bitmaps():
     """Calls on two streams in flight at once (one spilling into the overflow bitmaps, one not)
     each equal the same call made alone: the index's bitmaps and work counters are handed over
@@ -744,16 +772,17 @@ def _golden(name):
         return json.load(f)
 
 
-def _compare_fullsize(g, w, h, Qd):
+def _compare_fullsize(g, w, h, Qd, tables=True):
     """Tables, probe sets, candidate counts and top-k of the sampled queries against the oracle's
     stored values; every query call covers the whole batch (the benchmark's launch shape)."""
     rows = np.asarray(g["queries"], dtype=np.int64)
-    print(f"{g['workload']}: {g['L']} tables against the oracle", flush=True)
-    sizes = F().fpp_index_table_sizes(h)
-    for t, rec in enumerate(g["tables"]):
-        off, ids = F().fpp_debug_export_table(h, t)
-        assert sizes[t] == rec["size"] and int(np.max(np.diff(off))) == rec["max_bucket"], t
-        assert table_digest(off, ids) == rec["sha256"], t
+    if tables:
+        print(f"{g['workload']}: {g['L']} tables against the oracle", flush=True)
+        sizes = F().fpp_index_table_sizes(h)
+        for t, rec in enumerate(g["tables"]):
+            off, ids = F().fpp_debug_export_table(h, t)
+            assert sizes[t] == rec["size"] and int(np.max(np.diff(off))) == rec["max_bucket"], t
+            assert table_digest(off, ids) == rec["sha256"], t
     Qs = Qd[torch.from_numpy(rows).cuda()].contiguous()
     for qp, ref in g["fp32"].items():
         print(f"{g['workload']}: FP32 path, qProbes {qp}", flush=True)
@@ -808,7 +837,12 @@ def test_c5_shape_against_oracle():
     Xd = torch.from_numpy(w.X).cuda()
     h = F().fpp_build_index(Xd, g["L"], w.D, w.alpha, w.iProbes, g["seed"], l=w.l, stores=("fp8",))
     try:
-        _compare_fullsize(g, w, h, torch.from_numpy(w.Q).cuda())
+        Qd = torch.from_numpy(w.Q).cuda()
+        _compare_fullsize(g, w, h, Qd)
+        # every query deduplicated by id range (39 ranges of 2^18 ids, two probe chunks)
+        print("c5 shape: dedup by id range", flush=True)
+        F().fpp_debug_set_partition_threshold(h, 0, -1)
+        _compare_fullsize(g, w, h, Qd, tables=False)
     finally:
         F().fpp_free_index(h)
         del Xd
