@@ -199,44 +199,55 @@ __device__ __forceinline__ bool reports_row(int g) {
   return (g & (G / U - 1)) == 0;
 }
 
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-  const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// Bitonic stages j = jtop, ..., 1 (jtop <= 64) of stage k on a 128-key chunk held as two keys per
-// lane (indices i0 = base + lane, i1 = i0 + 64).
-__device__ __forceinline__ void chunk_stages(uint64_t& a, uint64_t& b, int i0, int k, int jtop) {
-  const int lane = threadIdx.x & 63;
-  for (int j = jtop; j > 0; j >>= 1) {
-    if (j == 64) {
-      const bool desc = (i0 & k) == 0;
-      if (desc ? (a < b) : (a > b)) {
-        const uint64_t t = a;
-        a = b;
-        b = t;
-      }
-    } else {
-      const uint64_t oa = shfl_xor_u64(a, j), ob = shfl_xor_u64(b, j);
-      const bool lower = (lane & j) == 0;
-      const bool da = (i0 & k) == 0, db = ((i0 + 64) & k) == 0;
-      const uint64_t amx = a > oa ? a : oa, amn = a > oa ? oa : a;
-      const uint64_t bmx = b > ob ? b : ob, bmn = b > ob ? ob : b;
-      a = (lower == da) ? amx : amn;
-      b = (lower == db) ? bmx : bmn;
+// One bitonic stage (partner distance J, block size k) on a 128-key chunk held as two keys per
+// lane (indices i0 = base + lane, i1 = i0 + 64). J is a compile-time constant, so every exchange
+// is a DPP move or a row swap (no LDS round trip): the stages form one dependent chain, and
+// their latency is what a compaction costs.
+template <int J>
+__device__ __forceinline__ void chunk_stage(uint64_t& a, uint64_t& b, int i0, int k) {
+  if constexpr (J == 64) {
+    const bool desc = (i0 & k) == 0;
+    if (desc ? (a < b) : (a > b)) {
+      const uint64_t t = a;
+      a = b;
+      b = t;
     }
+  } else {
+    const uint64_t oa = xor_lanes<J>(a), ob = xor_lanes<J>(b);
+    const bool lower = (threadIdx.x & J) == 0;
+    const bool da = (i0 & k) == 0, db = ((i0 + 64) & k) == 0;
+    const uint64_t amx = a > oa ? a : oa, amn = a > oa ? oa : a;
+    const uint64_t bmx = b > ob ? b : ob, bmn = b > ob ? ob : b;
+    a = (lower == da) ? amx : amn;
+    b = (lower == db) ? bmx : bmn;
   }
 }
 
+// Stages J = JTOP, JTOP / 2, ..., 1 of block size k.
+template <int JTOP>
+__device__ __forceinline__ void chunk_stages(uint64_t& a, uint64_t& b, int i0, int k) {
+  chunk_stage<JTOP>(a, b, i0, k);
+  if constexpr (JTOP > 1) chunk_stages<JTOP / 2>(a, b, i0, k);
+}
+
+// Block sizes k = 2, 4, ..., K of the chunk (K <= 128): the chunk sorted, descending where
+// (i0 & K) == 0 and ascending elsewhere.
+template <int K>
+__device__ __forceinline__ void chunk_sort(uint64_t& a, uint64_t& b, int i0) {
+  if constexpr (K > 2) chunk_sort<K / 2>(a, b, i0);
+  chunk_stages<K / 2>(a, b, i0, K);
+}
+
 // Block-wide bitonic sort (descending) of n keys in LDS, n a power of two >= 128. Stages with a
-// partner distance below 128 run in registers (two keys per lane, shuffles), the others in LDS.
+// partner distance below 128 run in registers (two keys per lane, DPP moves and row swaps), the
+// others in LDS.
 __device__ __noinline__ void block_sort_desc(uint64_t* key, int n) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int chunks = n >> 7;
   for (int c = wave; c < chunks; c += kWaves) {
     const int i0 = (c << 7) + lane;
     uint64_t a = key[i0], b = key[i0 + 64];
-    for (int k = 2; k <= 128; k <<= 1) chunk_stages(a, b, i0, k, k >> 1);
+    chunk_sort<128>(a, b, i0);
     key[i0] = a;
     key[i0 + 64] = b;
   }
@@ -259,7 +270,7 @@ __device__ __noinline__ void block_sort_desc(uint64_t* key, int n) {
     for (int c = wave; c < chunks; c += kWaves) {
       const int i0 = (c << 7) + lane;
       uint64_t a = key[i0], b = key[i0 + 64];
-      chunk_stages(a, b, i0, k, 64);
+      chunk_stages<64>(a, b, i0, k);
       key[i0] = a;
       key[i0 + 64] = b;
     }
