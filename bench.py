@@ -196,7 +196,7 @@ def timed_steps(torch, F, h, Qd, k, qp, store, steps, warmup):
 
 
 def serving_run(torch, F, h, Qd, *, store, qps_offered, n_queries, k_choices, qp_choices, seed,
-                n_streams=4, max_batch=2048):
+                n_streams=4, max_batch=8192):
     """Open-loop Poisson arrivals; latency = completion - scheduled arrival (queueing included).
 
     The offered load is sustained when (a) by the last scheduled arrival at least 99% of the
