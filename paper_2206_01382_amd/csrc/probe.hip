@@ -372,6 +372,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   const uint16_t* Cq = lc + (size_t)q * LF * D;
   float* tops = pre + (size_t)l * L * (M + 1);             // [L] best pair of every table
   float* sel = tops + L;                                    // one value
+  float* heads = sel + 1;                                   // [3L] pairs (0,0), (0,1), (1,0)
   if (M % 4 == 0) {
     // 16-byte loads, eight per thread in flight before their LDS stores
     const int per = M / 4, total4 = LF * per;
@@ -455,6 +456,31 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
       for (int u = 0; u < L; ++u) {
         const float w = tops[u];
         r += (w > v || (w == v && u < t)) ? 1 : 0;
+      }
+      if ((uint64_t)r == qP - 1) *sel = v;
+    }
+    __syncthreads();
+    mn = fmaxf(mn, *sel);
+  } else if (!gap && l == 2 && D >= 2 && qP <= 3 * (uint64_t)L && L <= kRankTables) {
+    // A tighter lo for up to three probes per table: the pairs at list positions (0, 0), (0, 1)
+    // and (1, 0) of every table are 3L distinct pairs with known scores, so the qP-th largest of
+    // them is reached by at least qP pairs: cnt(lo) >= qP.
+    const int H = 3 * L;
+    for (int t = tid; t < L; t += kProbeThreads) {
+      const float a0 = ls.get(2 * t, 0), a1 = ls.get(2 * t, 1);
+      const float b0 = ls.get(2 * t + 1, 0), b1 = ls.get(2 * t + 1, 1);
+      heads[3 * t] = a0 + b0;
+      heads[3 * t + 1] = a0 + b1;
+      heads[3 * t + 2] = a1 + b0;
+    }
+    __syncthreads();
+    for (int c = tid; c < H; c += kProbeThreads) {
+      const float v = heads[c];
+      int r = 0;
+#pragma unroll 4
+      for (int u = 0; u < H; ++u) {
+        const float w = heads[u];
+        r += (w > v || (w == v && u < c)) ? 1 : 0;
       }
       if ((uint64_t)r == qP - 1) *sel = v;
     }
@@ -571,7 +597,7 @@ int probe_prefix(const fpp_index* ix, int32_t qcap) {
   const int64_t per_t = (2LL * qcap + ix->L - 1) / ix->L;
   while (want < per_t && want < ix->D) want <<= 1;
   if (want > ix->D) want = ix->D;
-  while (want > 1 && (LF * (want + 1) + ix->L + 1) * 4 > 30 * 1024) want >>= 1;
+  while (want > 1 && (LF * (want + 1) + 4 * ix->L + 1) * 4 > 30 * 1024) want >>= 1;
   return want;
 }
 
@@ -591,8 +617,8 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
                                bool only_unfinished) {
   if (m <= 0) return hipSuccess;
   const int M = probe_prefix(ix, qcap);
-  const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + ix->L + 1) * 4;
-  if (lds > 64 * 1024) {   // at most 82 KB (L = 4096, l = 2, M = 1), within the 160 KB of a CU
+  const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + 4 * (size_t)ix->L + 1) * 4;
+  if (lds > 64 * 1024) {   // at most 131 KB (L = 4096, l = 2, M = 1), within the 160 KB of a CU
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(probe_kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
