@@ -372,7 +372,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
   const uint16_t* Cq = lc + (size_t)q * LF * D;
   float* tops = pre + (size_t)l * L * (M + 1);             // [L] best pair of every table
   float* sel = tops + L;                                    // one value
-  float* heads = sel + 1;                                   // [3L] pairs (0,0), (0,1), (1,0)
+  float* heads = sel + 1;   // [3L] pairs (0,0), (0,1), (1,0); allocated when qcap <= 3L, l = 2
   if (M % 4 == 0) {
     // 16-byte loads, eight per thread in flight before their LDS stores
     const int per = M / 4, total4 = LF * per;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
     }
     __syncthreads();
     mn = fmaxf(mn, *sel);
-  } else if (!gap && l == 2 && D >= 2 && qP <= 3 * (uint64_t)L && L <= kRankTables) {
+  } else if (!gap && l == 2 && D >= 2 && (uint64_t)qcap <= 3 * (uint64_t)L && L <= kRankTables) {
     // A tighter lo for up to three probes per table: the pairs at list positions (0, 0), (0, 1)
     // and (1, 0) of every table are 3L distinct pairs with known scores, so the qP-th largest of
     // them is reached by at least qP pairs: cnt(lo) >= qP.
@@ -586,6 +586,13 @@ __global__ __launch_bounds__(kProbeThreads) void probe_kernel(
 
 }  // namespace
 
+// LDS floats of the probe kernel besides the list prefixes: the tables' best pairs, one value,
+// and the 3L leading pairs when the search bracket uses them (l = 2, qcap <= 3L)
+static int64_t probe_extra_floats(const fpp_index* ix, int32_t qcap) {
+  const bool heads = ix->l == 2 && (int64_t)qcap <= 3LL * ix->L;
+  return (int64_t)ix->L + 1 + (heads ? 3LL * ix->L : 0);
+}
+
 // Prefix length of each sorted list staged in LDS: enough for about twice the average number of
 // probes per table, at most D and at most 30 KB of LDS per query. Small prefixes keep many
 // queries resident per CU, which hides the latency of the walks; entries past the prefix come
@@ -597,7 +604,7 @@ int probe_prefix(const fpp_index* ix, int32_t qcap) {
   const int64_t per_t = (2LL * qcap + ix->L - 1) / ix->L;
   while (want < per_t && want < ix->D) want <<= 1;
   if (want > ix->D) want = ix->D;
-  while (want > 1 && (LF * (want + 1) + 4 * ix->L + 1) * 4 > 30 * 1024) want >>= 1;
+  while (want > 1 && (LF * (want + 1) + probe_extra_floats(ix, qcap)) * 4 > 30 * 1024) want >>= 1;
   return want;
 }
 
@@ -617,7 +624,7 @@ hipError_t launch_probe_select(const fpp_index* ix, const float* la, const uint1
                                bool only_unfinished) {
   if (m <= 0) return hipSuccess;
   const int M = probe_prefix(ix, qcap);
-  const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + 4 * (size_t)ix->L + 1) * 4;
+  const size_t lds = 64 + ((size_t)ix->L * ix->l * (M + 1) + probe_extra_floats(ix, qcap)) * 4;
   if (lds > 64 * 1024) {   // at most 131 KB (L = 4096, l = 2, M = 1), within the 160 KB of a CU
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(probe_kernel),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
