@@ -6,16 +6,18 @@
 // s = fl32(|y1_a| + |y2_b|) (l = 2; s = |y_a| for l = 1), in the order (s desc, table asc,
 // position in list 1 asc, position in list 2 asc). Sorting every function's D outputs, as the
 // list-based path does, is most of the work of hashing. Here one workgroup owns one query:
-//   1. it rotates all L * l functions and records each function's best and second-best |y| in
-//      LDS;
+//   1. it rotates all L * l functions and records each function's best and second-best |y|,
+//      and its best output, in LDS;
 //   2. every table holds the pairs at positions (0, 0), (0, 1) and (1, 0) (l = 1: positions 0
 //      and 1) with scores known from those two values, so the qProbes-th best of these 3L
 //      scores, mn, is a lower bound of the qProbes-th best pair overall;
 //   3. an output y_a of function f can only be in a pair scoring >= mn if fl32(|y_a| + M) >= mn,
 //      with M the best |y| of the table's other function (float addition is monotone), so only
 //      tables whose best pair reaches mn matter (about a third of them at one probe per two
-//      tables): their functions are rotated again (the same expression tree, so the same values)
-//      and only the outputs passing that test are written to LDS. Every output ranking above an
+//      tables). Of their functions, one whose second-best |y| fails that test contributes only its
+//      best output, recorded in pass 1 (about two thirds of them); the others are rotated again
+//      (the same expression tree, so the same values) and only the outputs passing that test are
+//      written to LDS. Every output ranking above an
 //      emitted one in its list is emitted too, so an output's position in its list is its rank
 //      among the emitted outputs of its function;
 //   4. the emitted outputs of each table are paired, pairs scoring >= mn are ranked by the full
@@ -55,7 +57,7 @@ struct HPState {
 
 // LDS carve-up for LF functions and L tables (byte offsets, 8-byte aligned arrays first).
 struct HPLayout {
-  size_t ent, grp, pkey, pval, rk, M1, M2, cnt, start, tops, act, state, total;
+  size_t ent, grp, pkey, pval, rk, M1, M2, cnt, start, tops, act, by, bj, state, total;
   __host__ __device__ HPLayout(int LF, int L, int l) {
     size_t o = 0;
     ent = o;   o += (size_t)kEntCap * 8;
@@ -69,6 +71,8 @@ struct HPLayout {
     start = o; o += (size_t)(LF + 1) * 4;
     tops = o;  o += (size_t)(l == 2 ? 3 : 2) * L * 4;
     act = o;   o += (size_t)LF * 4;
+    by = o;    o += (size_t)LF * 4;
+    bj = o;    o += (size_t)LF * 4;
     rk = o;    o += (size_t)kEntCap * 2;
     total = (o + 15) / 16 * 16;
   }
@@ -122,9 +126,12 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
   float* tops = reinterpret_cast<float*>(smem + lo.tops);
   uint16_t* rk = reinterpret_cast<uint16_t*>(smem + lo.rk);
   int32_t* act = reinterpret_cast<int32_t*>(smem + lo.act);
+  float* BY = reinterpret_cast<float*>(smem + lo.by);      // each function's best output y
+  int32_t* BJ = reinterpret_cast<int32_t*>(smem + lo.bj);  // and its index
   const float* row = V + (size_t)q * ldv;
 
-  // ---- 1. rotations; each function's best and second-best |y|
+  // ---- 1. rotations; each function's best and second-best |y|, and its best output (the
+  // first in list order: largest |y|, then smallest index)
   for (int base = 0; base < LF; base += IPB) {
     const int item = base + g;
     const bool valid = item < LF;   // uniform over the item's lanes
@@ -134,21 +141,33 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
     load_sign_bits<P, E>(sign_bits, valid ? item : 0, j0, sw);
     rotate_item_bits<P>(v, sw, li);
     float m1 = -1.0f, m2 = -1.0f;   // below every |y|
+    float by = 0.0f;
+    int bj = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const float a = (!HALF || j0 + e < D) ? fabsf(v[e]) : -1.0f;   // listed outputs only
       m2 = __builtin_amdgcn_fmed3f(m1, m2, a);   // m1 >= m2: the new second best
+      const bool gt = a > m1;                    // strictly: the smaller index keeps a tie
+      by = gt ? v[e] : by;
+      bj = gt ? j0 + e : bj;
       m1 = fmaxf(m1, a);
     }
 #pragma unroll
     for (int o = 1; o < LPI; o <<= 1) {
       const float p1 = xor_lanes_n(m1, o), p2 = xor_lanes_n(m2, o);
+      const float pby = xor_lanes_n(by, o);
+      const int pbj = xor_lanes_n(bj, o);
       m2 = fmaxf(fminf(m1, p1), fmaxf(m2, p2));
+      const bool take = p1 > m1 || (p1 == m1 && pbj < bj);
+      by = take ? pby : by;
+      bj = take ? pbj : bj;
       m1 = fmaxf(m1, p1);
     }
     if (valid && li == 0) {
       M1[item] = m1;
       M2[item] = m2;
+      BY[item] = by;
+      BJ[item] = bj;
     }
   }
   for (int i = tid; i < LF; i += bs) cnt[i] = 0u;
@@ -191,13 +210,25 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
   __syncthreads();
   const float mn = st->mn;
 
-  // ---- 3. the functions of the tables whose best pair reaches mn, rotated again; emit the
-  // outputs that can reach mn
+  // ---- 3. the functions of the tables whose best pair reaches mn: a function whose second-best
+  // output cannot reach mn (with the other function's best) contributes only its best output,
+  // known from pass 1; the others are rotated again and emit every output that can reach mn
   for (int t = tid; t < L; t += bs) {
     if (tops[(l == 2 ? 3 : 2) * t] >= mn) {
-      const uint32_t x = atomicAdd(&st->nact, (uint32_t)l);
-      act[x] = l * t;
-      if (l == 2) act[x + 1] = 2 * t + 1;
+      for (int f = 0; f < l; ++f) {
+        const int item = l * t + f;
+        const float mo = l == 2 ? M1[item ^ 1] : 0.0f;
+        const float s2 = l == 2 ? M2[item] + mo : M2[item];
+        if (s2 >= mn) {
+          act[atomicAdd(&st->nact, 1u)] = item;
+        } else {
+          const uint32_t x = atomicAdd(&st->ecount, 1u);
+          if (x < (uint32_t)kEntCap) {
+            ent[x] = pack_entry(item, BJ[item], BY[item]);
+            atomicAdd(&cnt[item], 1u);
+          }
+        }
+      }
     }
   }
   __syncthreads();
