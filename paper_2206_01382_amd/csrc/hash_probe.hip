@@ -130,13 +130,18 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
   int32_t* BJ = reinterpret_cast<int32_t*>(smem + lo.bj);  // and its index
   const float* row = V + (size_t)q * ldv;
 
+  // the lane's elements of the query, loaded once for both passes
+  float xq[E];
+  load_elems<E, VEC>(row, d, j0, xq);
+
   // ---- 1. rotations; each function's best and second-best |y|, and its best output (the
   // first in list order: largest |y|, then smallest index)
   for (int base = 0; base < LF; base += IPB) {
     const int item = base + g;
     const bool valid = item < LF;   // uniform over the item's lanes
     float v[E];
-    load_elems<E, VEC>(row, d, j0, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = xq[e];
     uint32_t sw[3];
     load_sign_bits<P, E>(sign_bits, valid ? item : 0, j0, sw);
     rotate_item_bits<P>(v, sw, li);
@@ -238,7 +243,8 @@ __global__ __launch_bounds__(512) void hash_probe_kernel(
     const bool valid = idx < nact;
     const int item = valid ? act[idx] : 0;
     float v[E];
-    load_elems<E, VEC>(row, d, j0, v);
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = xq[e];
     uint32_t sw[3];
     load_sign_bits<P, E>(sign_bits, item, j0, sw);
     rotate_item_bits<P>(v, sw, li);
