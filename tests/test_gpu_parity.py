@@ -62,6 +62,12 @@ CONFIGS = {
     # d not a multiple of 4: element loads in the hash kernels, ragged row chunks in the gather
     "odd_d30_D32": dict(kind="cl", n=2_500, d=30, L=3, D=32, l=2, alpha=0.4, iProbes=2, m=20,
                         centers=8, spread=0.4),
+    # the largest sizes the boundary takes: d = 1024 (P = 1024, a whole wave per rotation) with 16
+    # buckets per point, and D = 2048 (P = 2048) for l = 1
+    "max_d1024_D1024_ip16": dict(kind="cl", n=3_000, d=1024, L=2, D=1024, l=2, alpha=0.5, iProbes=16,
+                                 m=10, centers=4, spread=0.4),
+    "max_D2048_l1_ip16": dict(kind="cl", n=1_500, d=48, L=2, D=2048, l=1, alpha=0.3, iProbes=16, m=10,
+                              centers=6, spread=0.4),
 }
 SEED = 1234
 
@@ -663,7 +669,7 @@ def test_heuristic_builds_bit_exact(name):
 
 # ----------------------------------------------------------------------------------------------
 # precision stores
-@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64"])
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "c1_gauss_10k_d64", "max_d1024_D1024_ip16"])
 def test_stores_bit_exact(name):
     w, oi, h, Xd, Qd = built(name)
     b, _ = F().fpp_debug_export_store(h, "bf16")
@@ -674,7 +680,7 @@ def test_stores_bit_exact(name):
     np.testing.assert_array_equal(c.cpu().numpy(), oc)
 
 
-@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256"])
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "max_d1024_D1024_ip16"])
 @pytest.mark.parametrize("store", ["bf16", "fp8"])
 def test_query_low_precision_with_rerank(name, store):
     w, oi, h, Xd, Qd = built(name)
@@ -709,6 +715,25 @@ def test_query_low_precision_without_rerank(name, store):
         oids[r], osc[r] = O.topk_order(deq[cand] @ w["Q"][r].astype(np.float64), cand, k)
     swaps = check_topk(deq, w["Q"], gi, gs, oids, osc)
     assert swaps <= swap_budget(gi.size), swaps
+
+
+@pytest.mark.parametrize("store", ["fp32", "bf16", "fp8"])
+def test_maximum_sizes_k512_rerank512(store):
+    """k = 512 with a rerank of R = 512 at d = 1024, the largest k, R and d the boundary takes:
+    the FP32 top-512 (and the reranked low-precision top-512) against the oracle's."""
+    w, oi, h, Xd, Qd = built("max_d1024_D1024_ip16")
+    k, qp = 512, 20_000   # about 600 candidates per query
+    if store == "fp32":
+        ids, sc, st = F().fpp_query(h, Qd, k, qp, stats=True)
+        oids, osc, ost = O.query(oi, w["Q"], k, qp)
+        np.testing.assert_array_equal(st.cpu().numpy(), ost)
+    else:
+        ids, sc = F().fpp_query(h, Qd, k, qp, store=store, rerank_R=512)
+        oids, osc, _ = O.query_reranked(oi, w["Q"], k, qp, R=512, storage=store)
+    gi = ids.cpu().numpy()
+    assert (gi >= 0).sum() > 0.9 * gi.size   # most rows hold 512 candidates
+    swaps = check_topk(w["X"], w["Q"], gi, sc.cpu().numpy(), oids, osc)
+    assert swaps <= swap_budget(ids.numel()), swaps
 
 
 def test_rerank_of_exactly_k_is_a_reorder_with_exact_scores():
