@@ -647,6 +647,19 @@ def main():
         log(f"{store}: {ms:.3f} ms/step {res[store]['qps']:.0f} q/s stages {stage.round(3)} "
             f"gather {res[store]['gbs']:.0f} GB/s unique/q {res[store]['unique']:.0f}")
 
+    # the batch paths at the smallest grid point reaching the target as well, so that the line
+    # also carries the coarse sweep's operating point
+    grid_pt = None
+    grid_qp = min((int(key.split("@")[1]) for key, r in recalls.items()
+                   if key.startswith("bf16@") and int(key.split("@")[1]) in QP_SWEEP and r >= 0.9),
+                  default=None)
+    if grid_qp is not None and grid_qp != chosen["bf16"]:
+        grid_pt = {"qProbes": grid_qp, "recall@10": recalls[f"bf16@{grid_qp}"]}
+        for store in ("fp32", "bf16"):
+            ms, _, _ = timed_steps(torch, F, h, Qd, k, grid_qp, store, args.steps, args.warmup)
+            grid_pt[f"{store}_batch_qps"] = round(w.Q.shape[0] / (ms / 1e3), 1)
+        log(f"at the grid point qProbes={grid_qp}: {grid_pt}")
+
     variants = None if args.no_variants else variant_report(torch, F, w, Xd, Qd, truth, k, args.steps, args.warmup)
 
     NB = (2 * w.D) ** w.l
@@ -761,6 +774,7 @@ def main():
                     "p50_ms": ser.get("p50_ms"), "p99_ms": ser.get("p99_ms"),
                     "completed_in_window": ser.get("completed_in_window"), "loads": serving},
         "candidate_sharing": sharing,
+        "at_grid_qprobes": grid_pt,
         "build_s": round(build_s, 3),
         "index_ids": info["total_ids"],
         "recall_sweep": recalls,
