@@ -4,14 +4,16 @@
 Workload (synthetic, seeded): n = 1,000,000 points, d = 128, a 1,000-centre Gaussian mixture on
 the unit sphere (spread 0.3); 10,000 queries from the same mixture; L = 100 tables of two
 concatenated cross-polytope hashes, D = 128 (65,536 buckets per table), alpha = 0.3, iProbes = 3;
-k = 10. qProbes (the total over all tables) is the smallest of 10, 20, 50, ..., 20,000 whose
-recall@10 over all 10,000 queries reaches 0.9; the sweep covers the workload's values read both
-as totals (10..200) and as per-table budgets (x L = 1,000..20,000).
+k = 10. qProbes (the total over all tables) is the smallest total whose recall@10 over all
+10,000 queries reaches 0.9: the grid 10, 20, 50, ..., 20,000 (the workload's values read both as
+totals, 10..200, and as per-table budgets, x L = 1,000..20,000), then integer bisection between
+the last grid value below 0.9 and the first at or above it.
 
 A step is one pass of the query path over the 10,000 resident queries (hash -> probe selection
--> gather/score/top-k [-> FP32 rerank]); the index build is timed separately. `value` is the
-queries/s of the BF16-store + FP32-rerank path over the timed steps; the plain FP32 path, the
-serving loop (Poisson arrivals, p50/p99 latency) and the build are reported beside it.
+-> gather/score/top-k [-> FP32 rerank]) with the BF16 store and an FP32 rerank; the index build
+is timed separately. `value` is the sustained rate of the serving loop (open-loop Poisson
+arrivals, continuous batching, BF16 + FP32 rerank) at that qProbes, with its p50/p99 latency;
+the FP32 and FP8 batch paths, the build and the other reports are printed beside it.
 
 Prints one JSON line.
 """
