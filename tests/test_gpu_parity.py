@@ -62,6 +62,11 @@ CONFIGS = {
     # d not a multiple of 4: element loads in the hash kernels, ragged row chunks in the gather
     "odd_d30_D32": dict(kind="cl", n=2_500, d=30, L=3, D=32, l=2, alpha=0.4, iProbes=2, m=20,
                         centers=8, spread=0.4),
+    # the fused hash-and-select kernel with items of 8 lanes (P = 128): D = P and D = P / 2
+    "fused_d128_D128": dict(kind="cl", n=3_000, d=128, L=8, D=128, l=2, alpha=0.3, iProbes=3, m=30,
+                            centers=10, spread=0.4),
+    "fused_half_d100_D64": dict(kind="cl", n=3_000, d=100, L=8, D=64, l=2, alpha=0.3, iProbes=3, m=30,
+                                centers=10, spread=0.4),
     # the largest sizes the boundary takes: d = 1024 (P = 1024, a whole wave per rotation) with 16
     # buckets per point, and D = 2048 (P = 2048) for l = 1
     "max_d1024_D1024_ip16": dict(kind="cl", n=3_000, d=1024, L=2, D=1024, l=2, alpha=0.5, iProbes=16,
@@ -306,7 +311,7 @@ def test_probe_sets_bit_exact(name):
 
 
 @pytest.mark.parametrize("name", ["l2_clustered", "c1_gauss_10k_d64", "manyL_d24_L40", "l1_L24_D16",
-                                  "wideD_d20_D64"])
+                                  "wideD_d20_D64", "fused_d128_D128", "fused_half_d100_D64"])
 def test_probe_sets_near_ties_bit_exact(name):
     """Probe budgets up to 2L take the fused hash-and-select kernel; vectors whose projections
     tie (zero, constant, basis vectors) emit more outputs than it holds, so those queries are
