@@ -120,13 +120,13 @@ def precision_report(torch, F, h, Xd, Qs, truth, k, qp, stores=("bf16", "fp8")):
     return out
 
 
-def smallest_qprobes(rec, target=0.9):
-    """The smallest qProbes whose recall `rec(qp)` reaches the target: the grid QP_SWEEP, then
-    integer bisection between the last grid value below the target (or 0) and the first at or
-    above it. Probe sets are nested in qProbes, so recall rises with it. None if no grid value
-    reaches the target."""
+def smallest_qprobes(rec, target=0.9, grid=QP_SWEEP):
+    """The smallest qProbes whose recall `rec(qp)` reaches the target: the grid (QP_SWEEP by
+    default), then integer bisection between the last grid value below the target (or 0) and
+    the first at or above it. Probe sets are nested in qProbes, so recall rises with it. None if
+    no grid value reaches the target."""
     lo, hi = 0, None
-    for qp in QP_SWEEP:
+    for qp in grid:
         if rec(qp) >= target:
             hi = qp
             break
@@ -476,7 +476,8 @@ def candidate_sharing(F, h, Qd, qp, tables, NB):
 def run_secondary(args, name):
     """One JSON line for the precision-form (n = 1M, d = 300) or the large (n = 10M, d = 96)
     workload: build time, recall of each store with and without rerank, score errors and the
-    query rate of each store at the smallest swept qProbes reaching recall@10 >= 0.9."""
+    query rate of each store at the smallest qProbes reaching recall@10 >= 0.9 (the workload's
+    grid, then bisection; the large workload keeps its fixed probes per table)."""
     import torch
 
     import paper_2206_01382_amd as F
@@ -503,21 +504,25 @@ def run_secondary(args, name):
     Qs = Qd[:ns].contiguous()
     truth = ground_truth(torch, Xd, Qs, k)
     sweep = sorted({v * w.L for v in w.qprobes_per_table} | set(w.qprobes_per_table))
-    if args.qprobes:
-        sweep = [args.qprobes]
-    recalls, chosen = {}, None
-    for qp in sweep:
+    recalls = {}
+
+    def rec(qp):
         row = {}
         for store in ("fp32",) + stores:
             ids, _ = F.fpp_query(h, Qs, k, qp, store=store)
             row[store] = round(recall_at_10(ids.cpu().numpy(), truth), 4)
         recalls[str(qp)] = row
         log(f"recall qProbes={qp}: {row}")
-        if row[stores[-1]] >= 0.9:
-            chosen = qp
-            break
-    if chosen is None:
-        chosen = sweep[-1]
+        return row[stores[-1]]
+    if args.qprobes:
+        rec(args.qprobes)
+        chosen = args.qprobes
+    elif name.startswith("c5"):
+        # the workload fixes the probes per table (the first of its values reaching 0.9)
+        chosen = next((qp for qp in sweep if rec(qp) >= 0.9), sweep[-1])
+    else:
+        # as for the headline: the workload's grid, then bisection for the smallest total
+        chosen = smallest_qprobes(rec, grid=sweep) or sweep[-1]
     precision = precision_report(torch, F, h, Xd, Qs, truth, k, chosen, stores=stores)
     res = {}
     for store in ("fp32",) + stores:
