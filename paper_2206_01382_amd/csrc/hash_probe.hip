@@ -1,5 +1,5 @@
 // Query hashing and probe selection in one kernel, for probe budgets of up to about two probes per
-// table and D = P <= 256 or D = P / 2 <= 128 (Section 3.4, multi-probing for querying; Section 2.2
+// table and D = P <= 256 or D = P / 2 <= 256 (Section 3.4, multi-probing for querying; Section 2.2
 // Eq. 1 for the hash; qProbes is a total over the L tables).
 //
 // The selection needs the qProbes best (table, bucket) pairs of a query by the pair score
@@ -408,10 +408,13 @@ hipError_t launch_hp_p(const fpp_index* ix, const float* V, int64_t m, int ldv, 
 bool hash_probe_applies(const fpp_index* ix, int32_t qp_max, int32_t probe_score, int32_t store) {
   if (probe_score != FPP_PROBE_SUM || store == FPP_STORE_SIMHASH) return false;
   const bool full = ix->D == ix->P && ix->P >= 16 && ix->P <= 256;
-  // at P = 512 the second rotation of the active tables costs more than the list kernel's sort
-  // saves (measured at d = 300, L = 128, qProbes = 200), so D = P / 2 stops at P = 256
-  const bool half = 2 * ix->D == ix->P && ix->P >= 32 && ix->P <= 256;
+  // D = P / 2 up to P = 512; at P = 512 only for at most one probe per table: beyond that the
+  // second rotation of the active tables costs more than the list kernel's sort saves (measured
+  // at d = 300, L = 128: 2.58 against 3.39 ms per 10,000 queries at qProbes = 101, 4.39 against
+  // 4.10 ms at qProbes = 200)
+  const bool half = 2 * ix->D == ix->P && ix->P >= 32 && ix->P <= 512;
   if (!full && !half) return false;
+  if (ix->P == 512 && (int64_t)qp_max > ix->L) return false;
   if (ix->L > kMaxTables || (ix->l != 1 && ix->l != 2)) return false;
   if ((int64_t)ix->L * ix->D * ix->D >= ((int64_t)1 << 32) || (ix->NB + 1) * (int64_t)ix->L >= ((int64_t)1 << 32))
     return false;
@@ -440,6 +443,7 @@ hipError_t launch_hash_probe(const fpp_index* ix, const float* V, int64_t m, int
       case 64: FPP_HP(64, true);
       case 128: FPP_HP(128, true);
       case 256: FPP_HP(256, true);
+      case 512: FPP_HP(512, true);
       default: return hipErrorInvalidValue;
     }
   }

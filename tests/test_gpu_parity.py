@@ -883,7 +883,8 @@ def test_full_size_precision_form_sampled():
     """n = 1M, d = 300 (P = 512), L = 128, D = 256, l = 2, alpha = 0.2, iProbes = 3 with the BF16
     and FP8 stores, 10,000 queries in one launch: sampled rows of both stores bit-exact, sampled
     probe sets bit-exact, and the sampled queries' FP32 top-k and unreranked BF16 / FP8 top-k equal
-    to exact search (on the exact or the dequantised rows) over the candidates their probes select."""
+    to exact search (on the exact or the dequantised rows) over the candidates their probes select,
+    at 101 probes (fused hash-and-select kernel) and 200 (list kernels)."""
     w = synthdata.workload("c3_cluster_1m_d300")
     Xd = torch.from_numpy(w.X).cuda()
     h = F().fpp_build_index(Xd, w.L, w.D, w.alpha, w.iProbes, 42, l=w.l, stores=("bf16", "fp8"))
@@ -899,44 +900,46 @@ def test_full_size_precision_form_sampled():
         np.testing.assert_array_equal(sc8.cpu().numpy()[rows].view(np.uint32), os_.view(np.uint32))
         del b, c, sc8
         Qd = torch.from_numpy(w.Q).cuda()
-        qp = 200
-        shell = O.Index(X=w.X, L=w.L, D=w.D, l=w.l, P=512, alpha=w.alpha, iProbes=w.iProbes, seed=42, signs=S)
-        NB = O.n_buckets(w.D, w.l)
-        print("full-size c3: FP32 and approximate passes", flush=True)
-        gi, gs = F().fpp_query(h, Qd, 10, qp)
-        appr = {st: F().fpp_query(h, Qd, 10, qp, store=st, rerank_R=-1) for st in ("bf16", "fp8")}
-        gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
-        appr = {st: (a.cpu().numpy(), b.cpu().numpy()) for st, (a, b) in appr.items()}
-        tables = {}
+        # 101 probes (at most one per table: the fused hash-and-select kernel) and 200 (the list
+        # kernels)
+        for qp in (101, 200):
+            shell = O.Index(X=w.X, L=w.L, D=w.D, l=w.l, P=512, alpha=w.alpha, iProbes=w.iProbes, seed=42, signs=S)
+            NB = O.n_buckets(w.D, w.l)
+            print(f"full-size c3: qProbes {qp}: FP32 and approximate passes", flush=True)
+            gi, gs = F().fpp_query(h, Qd, 10, qp)
+            appr = {st: F().fpp_query(h, Qd, 10, qp, store=st, rerank_R=-1) for st in ("bf16", "fp8")}
+            gi, gs = gi.cpu().numpy(), gs.cpu().numpy()
+            appr = {st: (a.cpu().numpy(), b.cpu().numpy()) for st, (a, b) in appr.items()}
+            tables = {}
 
-        def local(ids, cand):      # candidate ids -> rows of the candidate submatrix
-            ids = ids.astype(np.int64)
-            pos = np.searchsorted(cand, np.maximum(ids, 0))
-            ok = ids >= 0
-            assert np.all(cand[np.minimum(pos[ok], len(cand) - 1)] == ids[ok])
-            return np.where(ok, pos, -1)
+            def local(ids, cand):      # candidate ids -> rows of the candidate submatrix
+                ids = ids.astype(np.int64)
+                pos = np.searchsorted(cand, np.maximum(ids, 0))
+                ok = ids >= 0
+                assert np.all(cand[np.minimum(pos[ok], len(cand) - 1)] == ids[ok])
+                return np.where(ok, pos, -1)
 
-        for r in (0, 4_321, w.Q.shape[0] - 1):
-            print(f"full-size c3: query {r}", flush=True)
-            pr = O.probes(shell, w.Q[r], qp)
-            gp = F().fpp_debug_probes(h, Qd[r:r + 1].contiguous(), qp).cpu().numpy()[0]
-            assert sorted(gp.tolist()) == sorted(pr.tolist())
-            cand = []
-            for p in pr:
-                t, bk = divmod(int(p), NB)
-                if t not in tables:
-                    tables[t] = F().fpp_debug_export_table(h, t)
-                off, ids = tables[t]
-                cand.append(ids[off[bk]:off[bk + 1]])
-            cand = np.unique(np.concatenate(cand).astype(np.int64))
-            pos = np.arange(len(cand))
-            q = w.Q[r:r + 1]
-            Xc = w.X[cand]
-            ri, rs = O.topk_order(Xc.astype(np.float64) @ q[0].astype(np.float64), pos, 10)
-            check_topk(Xc, q, local(gi[r:r + 1], cand), gs[r:r + 1], ri[None], rs[None], 10, 300)
-            for st, (ai, asc) in appr.items():
-                dq = O.dequantized_store(Xc, st)
-                bi, bs = O.topk_order(dq @ q[0].astype(np.float64), pos, 10)
-                check_topk(dq, q, local(ai[r:r + 1], cand), asc[r:r + 1], bi[None], bs[None], 10, 300, st)
+            for r in (0, 4_321, w.Q.shape[0] - 1):
+                print(f"full-size c3: qProbes {qp}, query {r}", flush=True)
+                pr = O.probes(shell, w.Q[r], qp)
+                gp = F().fpp_debug_probes(h, Qd[r:r + 1].contiguous(), qp).cpu().numpy()[0]
+                assert sorted(gp.tolist()) == sorted(pr.tolist())
+                cand = []
+                for p in pr:
+                    t, bk = divmod(int(p), NB)
+                    if t not in tables:
+                        tables[t] = F().fpp_debug_export_table(h, t)
+                    off, ids = tables[t]
+                    cand.append(ids[off[bk]:off[bk + 1]])
+                cand = np.unique(np.concatenate(cand).astype(np.int64))
+                pos = np.arange(len(cand))
+                q = w.Q[r:r + 1]
+                Xc = w.X[cand]
+                ri, rs = O.topk_order(Xc.astype(np.float64) @ q[0].astype(np.float64), pos, 10)
+                check_topk(Xc, q, local(gi[r:r + 1], cand), gs[r:r + 1], ri[None], rs[None], 10, 300)
+                for st, (ai, asc) in appr.items():
+                    dq = O.dequantized_store(Xc, st)
+                    bi, bs = O.topk_order(dq @ q[0].astype(np.float64), pos, 10)
+                    check_topk(dq, q, local(ai[r:r + 1], cand), asc[r:r + 1], bi[None], bs[None], 10, 300, st)
     finally:
         F().fpp_free_index(h)
