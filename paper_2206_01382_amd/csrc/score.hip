@@ -545,12 +545,20 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
 
     // CSR ranges of probes [c, c + nc) into s_beg / s_pre (exclusive prefix of the lengths);
     // returns the chunk's entry count
-    auto scan_chunk = [&](int32_t c, int nc) -> uint32_t {
+    // (rc: the ranges come from the copy the entry count left at the tail of the bitmap region,
+    // a contiguous read, instead of the probe list and two offset lookups per probe)
+    uint32_t* rcache = nullptr;   // [np] range begins, then [np] lengths
+    auto scan_chunk = [&](int32_t c, int nc, bool rc = false) -> uint32_t {
       uint32_t beg = 0, len = 0;
       if (tid < nc) {
-        const uint32_t gb = pr[c + tid];
-        beg = p.offsets[gb];
-        len = p.offsets[gb + 1] - beg;
+        if (rc) {
+          beg = rcache[c + tid];
+          len = rcache[np + c + tid];
+        } else {
+          const uint32_t gb = pr[c + tid];
+          beg = p.offsets[gb];
+          len = p.offsets[gb + 1] - beg;
+        }
       }
       uint32_t ec;
       const uint32_t pre = block_excl_scan(len, ec, wsum);
@@ -617,12 +625,21 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       entries = ec;
       pc = kProbeChunk;
     } else if (np > kProbeChunk) {
+      // more than one chunk: the ranges are also copied to the tail of the workgroup's bitmap
+      // region (zero on entry), for the id-range passes below; the copy is cleared again if the
+      // query does not take them
+      if (2 * (int64_t)np <= p.bm_words) rcache = bitmap + (p.bm_words - 2 * (int64_t)np);
       for (int32_t c = 0; c < np; c += kProbeChunk) {
         const int nc = np - c < kProbeChunk ? np - c : kProbeChunk;
         uint32_t len = 0;
         if (tid < nc) {
           const uint32_t gb = pr[c + tid];
-          len = p.offsets[gb + 1] - p.offsets[gb];
+          const uint32_t beg = p.offsets[gb];
+          len = p.offsets[gb + 1] - beg;
+          if (rcache) {
+            rcache[c + tid] = beg;
+            rcache[np + c + tid] = len;
+          }
         }
         uint32_t tot;
         (void)block_excl_scan(len, tot, wsum);
@@ -631,8 +648,18 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     }
     const int pshift = p.part_shift;
     const int64_t nparts = (p.n + ((int64_t)1 << pshift) - 1) >> pshift;
-    const bool partitioned = (int64_t)entries > p.part_min && entries <= (uint64_t)p.bm_words &&
-                             nparts <= (int64_t)kMaxParts;
+    // the id buffer [0, entries) must stay clear of the range copy at the region's tail
+    const uint64_t room = (uint64_t)p.bm_words - (rcache ? 2 * (uint64_t)np : 0);
+    const bool partitioned = (int64_t)entries > p.part_min && entries <= room &&
+                             nparts <= (int64_t)kMaxParts && (np <= kProbeChunk || rcache);
+    if (rcache && !partitioned) {
+      // the region is the dedup bitmap on the other path: the copy returns to zero first
+      for (int32_t i = tid; i < 2 * np; i += kBlock) rcache[i] = 0u;
+      __threadfence();
+      __syncthreads();
+      rcache = nullptr;
+    }
+    const bool rc = rcache != nullptr;
 
     if (partitioned) {
       // ---- A': many entries. Pass 1 counts the entries of each id range, pass 2 writes their ids
@@ -640,7 +667,8 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       // `entries` words), pass 3 deduplicates each range in an LDS bitmap over its 2^pshift ids
       // (the set's memory) and queues the first occurrences. Three reads of the probed ids
       // and one write of them replace one device atomic per entry and the clearing of an n-bit
-      // bitmap.
+      // bitmap; with more than one probe chunk, passes 1 and 2 take the probe ranges from the
+      // copy the entry count made (a contiguous read) instead of two offset lookups per probe.
       uint32_t* buf = bitmap;
       const uint32_t E = (uint32_t)entries;
       static_assert(kMaxParts == kBlock, "one range count per thread");
@@ -649,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       for (int pass = 0; pass < 2; ++pass) {
         for (int32_t c = 0; c < np; c += kProbeChunk) {
           const int nc = np - c < kProbeChunk ? np - c : kProbeChunk;
-          const uint32_t ecc = scan_chunk(c, nc);
+          const uint32_t ecc = scan_chunk(c, nc, rc);
           for (uint32_t r = 0; r < ecc; r += kRound) {
             int32_t idv[kEPT];
             load_entries(r + (uint32_t)tid * kEPT, ecc, nc, idv);
@@ -702,8 +730,11 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         __syncthreads();
       }
       score_queue(true);
-      // the buffer returns to zero (it is the bitmap region), the set's memory to empty slots
+      // the buffer and the range copy return to zero (they are the bitmap region), the set's
+      // memory to empty slots
       for (uint32_t e = tid; e < E; e += kBlock) buf[e] = 0u;
+      if (rc)
+        for (int32_t i = tid; i < 2 * np; i += kBlock) rcache[i] = 0u;
       __threadfence();
     } else {
       uint32_t e0 = 0;     // next entry of the current chunk
