@@ -9,8 +9,9 @@ the GPU library.
     python tests/golden/make_fullsize_oracle.py c5     # -> tests/golden/c5_shape_oracle.json
 
 c2: the headline index (n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3,
-    seed 42) and 200 of its 10,000 queries (every 50th), at 50 probes in total and at 50 per
-    table, plus the BF16 and FP8 short lists of 100 reranked in FP64 at 50 probes.
+    seed 42) and 200 of its 10,000 queries (every 50th), at 27 probes in total (the smallest
+    total reaching recall@10 0.9 on these queries' batch), at 50 and at 50 per table, plus the
+    BF16 and FP8 short lists of 100 reranked in FP64 at 27 probes.
 c5: the large workload's data and hash shape (n = 10M, d = 96 -> P = 256, D = 256, l = 2,
     alpha = 0.1, iProbes = 2, seed 42) with 4 of its 64 tables, and 200 of its 100,000 queries
     (every 500th) at 100 probes per table (400 in total), FP32 and FP8 with the rerank of 100.
@@ -41,8 +42,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 SPECS = {
     "c2": dict(workload="c2_cluster_1m_d128", L=100, seed=42, q_stride=50,
-               qprobes=(50, 5000), rerank=dict(qprobes=50, R=100, stores=("bf16", "fp8")),
-               probes_at=50, out="c2_full_oracle.json"),
+               qprobes=(27, 50, 5000), rerank=dict(qprobes=27, R=100, stores=("bf16", "fp8")),
+               probes_at=27, out="c2_full_oracle.json"),
     "c5": dict(workload="c5_cluster_10m_d96", L=4, seed=42, q_stride=500,
                qprobes=(400,), rerank=dict(qprobes=400, R=100, stores=("fp8",)),
                probes_at=400, out="c5_shape_oracle.json"),

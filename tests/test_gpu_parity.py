@@ -840,8 +840,9 @@ def test_full_size_c2_against_oracle():
     """The headline index (n = 1M, d = 128, L = 100, D = 128, l = 2, alpha = 0.3, iProbes = 3)
     against the oracle's own index and answers (stored by tests/golden/make_fullsize_oracle.py):
     all 100 tables bit-exact, and for 200 queries spread over the 10,000-query batch the probe
-    sets (50 in total), the candidate counts and the FP32 top-10 at 50 probes and at 50 per
-    table, and the BF16 and FP8 paths with the FP32 rerank of 100."""
+    sets (27 in total, the benchmark's operating point), the candidate counts and the FP32
+    top-10 at 27 and 50 probes and at 50 per table, and the BF16 and FP8 paths with the FP32
+    rerank of 100 at 27 probes."""
     g = _golden("c2_full_oracle.json")
     w = synthdata.workload("c2_cluster_1m_d128")
     assert (g["n"], g["d"], g["L"], g["D"]) == (w.X.shape[0], w.X.shape[1], w.L, w.D)
