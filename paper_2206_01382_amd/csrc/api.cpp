@@ -378,6 +378,20 @@ static int build_impl(const float* X, int64_t n, int32_t d, int32_t L, int32_t D
     FPP_TRY(dalloc(&ix->fp8_scale, (size_t)n, &bytes));
   }
   if (o.stores & ((1 << FPP_STORE_BF16) | (1 << FPP_STORE_FP8))) FPP_HIP(launch_quantize(ix.get(), s));
+  if (ix->Xbf16) {
+    // an upper bound of the rows' norms, for the rerank's bound on the BF16 score error
+    uint32_t* nb = nullptr;
+    DeviceScratch nsc;
+    FPP_TRY(nsc.get(&nb, 1));
+    FPP_HIP(hipMemsetAsync(nb, 0, sizeof(uint32_t), s));
+    FPP_HIP(launch_row_norm_max(ix.get(), nb, s));
+    uint32_t bits = 0;
+    FPP_HIP(hipMemcpyAsync(&bits, nb, sizeof(bits), hipMemcpyDeviceToHost, s));
+    FPP_HIP(hipStreamSynchronize(s));
+    float v;
+    std::memcpy(&v, &bits, sizeof(v));
+    ix->xnorm_max = std::isfinite(v) ? v : -1.0f;
+  }
   if (sigF) {
     // signatures: the sorted lists of the first F functions of every point, packed to bits
     ix->sigF = sigF;
@@ -437,7 +451,7 @@ Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max
   ly.short_ld = (store == FPP_STORE_FP32 || R_opt < 0) ? 0 : short_list_len(R_opt, k_max);
   const int64_t LF = (int64_t)ix->L * ix->l;
   const int64_t sigw = store == FPP_STORE_SIMHASH ? ix->ldsig : 0;
-  const int64_t per_q = LF * ix->D * 6 + (int64_t)ly.qcap * 4 + 4 + (int64_t)ly.short_ld * 4 + sigw * 4 + 64;
+  const int64_t per_q = LF * ix->D * 6 + (int64_t)ly.qcap * 4 + 4 + (int64_t)ly.short_ld * 8 + sigw * 4 + 64;
   ly.mc = std::max<int64_t>(1, std::min<int64_t>(m, budget / per_q));
   ly.gbm = gbm_in_scratch;
   ly.grid = score_grid_blocks(ix);
@@ -450,8 +464,8 @@ Layout plan_layout(const fpp_index* ix, int64_t m, int32_t qp_max, int32_t k_max
   o = a256(o + (size_t)ly.mc * ly.qcap * 4);
   ly.off_np = o;
   o = a256(o + (size_t)ly.mc * 4);
-  ly.off_short = o;
-  o = a256(o + (size_t)ly.mc * ly.short_ld * 4);
+  ly.off_short = o;   // ids, then their approximate scores
+  o = a256(o + (size_t)ly.mc * ly.short_ld * 8);
   ly.off_qsig = o;
   o = a256(o + (size_t)ly.mc * sigw * 4);
   ly.off_gbm = o;
@@ -486,6 +500,8 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
   uint32_t* probes = (uint32_t*)(ws + ly.off_probes);
   int32_t* np = (int32_t*)(ws + ly.off_np);
   int32_t* shortl = (int32_t*)(ws + ly.off_short);
+  float* shortsc = (float*)(ws + ly.off_short) + (size_t)ly.mc * ly.short_ld;
+  const float bound_c = qs.store == FPP_STORE_BF16 ? bf16_rerank_bound(ix) : -1.0f;
   uint32_t* gbm = ly.gbm ? (uint32_t*)(ws + ly.off_gbm) : qs.gbm_ext;
   const int d = ix->d;
   for (int64_t c0 = 0; c0 < qs.m; c0 += ly.mc) {
@@ -532,6 +548,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     a.gbitmap = gbm;
     a.grid = ly.grid;
     a.short_ids = shortl;
+    a.short_sc = shortsc;
     a.short_ld = ly.short_ld;
     int32_t* ids_c = qs.ids_out;
     float* sc_c = qs.scores_out;
@@ -548,8 +565,8 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     FPP_HIP(launch_score(ix, a, s));
     FPP_TRY(mark());
     if (qs.store != FPP_STORE_FP32 && qs.R_opt >= 0) {
-      FPP_HIP(launch_rerank(ix, Qc, d, mc, shortl, ly.short_ld, a.k_arr, qs.k_uniform, qs.R_opt,
-                            off_c, ids_c, sc_c, s));
+      FPP_HIP(launch_rerank(ix, Qc, d, mc, shortl, shortsc, ly.short_ld, bound_c, a.k_arr,
+                            qs.k_uniform, qs.R_opt, off_c, ids_c, sc_c, s));
     }
     FPP_TRY(mark());
   }

@@ -64,6 +64,7 @@ struct fpp_index {
   uint16_t* Xbf16 = nullptr;      // device [n][ld16]
   uint8_t* Xfp8 = nullptr;        // device [n][ld8]
   float* fp8_scale = nullptr;     // device [n]
+  float xnorm_max = -1.0f;        // an upper bound of the rows' L2 norms (BF16 builds), else -1
   float* center_vec = nullptr;    // device [d] centring vector (centred builds only)
   uint32_t* Xsig = nullptr;       // device [n][ldsig] SimHash signatures
   int32_t sigF = 0;               // hash functions in a signature
@@ -187,16 +188,26 @@ struct ScoreArgs {
   int32_t* ids_out;
   float* scores_out;
   int32_t* short_ids;      // [m][short_ld] short lists (low-precision stores)
+  float* short_sc;         // [m][short_ld] their approximate scores (-inf past the list)
   int32_t short_ld;
   int64_t* stats;          // [m][3] or null
   uint32_t* gbitmap;       // overflow dedup bitmaps [grid][ceil(n/32)], zero on entry and exit
   int32_t grid;            // persistent blocks
 };
 hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s);
+// bound_c > 0: |approximate - FP32 score| <= bound_c * ||q|| for every stored row, and short_sc
+// holds the approximate scores; the rerank then skips the tail of a short list that cannot reach
+// the top k (the result is the same). bound_c <= 0: every listed row is rescored.
 hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m,
-                         const int32_t* short_ids, int short_ld, const int32_t* k_arr,
-                         int k_uniform, int R_opt, const int64_t* out_off, int32_t* ids_out,
-                         float* scores_out, hipStream_t s);
+                         const int32_t* short_ids, const float* short_sc, int short_ld,
+                         float bound_c, const int32_t* k_arr, int k_uniform, int R_opt,
+                         const int64_t* out_off, int32_t* ids_out, float* scores_out,
+                         hipStream_t s);
+// An upper bound of max_i ||x_i||_2 over the stored rows, as float bits (atomic max into *out,
+// which the caller zeroes).
+hipError_t launch_row_norm_max(const fpp_index* ix, uint32_t* out, hipStream_t s);
+// The rerank bound constant of the BF16 store (see launch_rerank), or -1 if unknown.
+float bf16_rerank_bound(const fpp_index* ix);
 int score_grid_blocks(const fpp_index* ix);
 int64_t overflow_bitmap_words(const fpp_index* ix);   // per score workgroup
 int32_t short_list_len(int32_t R_opt, int32_t k);

@@ -48,6 +48,23 @@ __global__ __launch_bounds__(256) void quant_bf16_kernel(const float* __restrict
   out[i] = c < d ? bf16_rne(X[r * ldx + c]) : (uint16_t)0;
 }
 
+// One wavefront per row: the float32 sum of squares, whose rounding (at most d / 64 + 6 steps)
+// and that of the square root are covered by the factor 1 + 2^-16, so the value is an upper bound
+// of the row's L2 norm; the maximum over rows by an integer atomic max on the (non-negative)
+// float bits.
+__global__ __launch_bounds__(256) void row_norm_max_kernel(const float* __restrict__ X, int64_t n,
+                                                           int d, int ldx, uint32_t* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (r >= n) return;
+  const float* x = X + r * ldx;
+  float ss = 0.0f;
+  for (int c = lane; c < d; c += 64) ss = fmaf(x[c], x[c], ss);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o);
+  if (lane == 0) atomicMax(out, __float_as_uint(sqrtf(ss) * 1.0000152587890625f));
+}
+
 // One wavefront per row. With sc_off >= 0 the scale is also stored inside the row at byte sc_off.
 __global__ __launch_bounds__(256) void quant_fp8_kernel(const float* __restrict__ X, int64_t n,
                                                         int d, int ldx, uint8_t* __restrict__ out,
@@ -100,6 +117,13 @@ hipError_t launch_quantize(const fpp_index* ix, hipStream_t s) {
     hipLaunchKernelGGL(quant_fp8_kernel, dim3((unsigned)((ix->n + 3) / 4)), dim3(256), 0, s, ix->X,
                        ix->n, ix->d, ix->ldx, ix->Xfp8, ix->ld8, ix->fp8_sc_off, ix->fp8_scale);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_row_norm_max(const fpp_index* ix, uint32_t* out, hipStream_t s) {
+  if (ix->n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(row_norm_max_kernel, dim3((unsigned)((ix->n + 3) / 4)), dim3(256), 0, s, ix->X,
+                     ix->n, ix->d, ix->ldx, out);
   return hipGetLastError();
 }
 

@@ -21,6 +21,8 @@
 // Keys are 64-bit: order-preserving float bits << 32 | (0xffffffff - id).
 // The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
 // scores exactly in float32 from the FP32 store.
+#include <cmath>
+
 #include "fpp_internal.hpp"
 #include "lanes.hpp"
 
@@ -336,6 +338,7 @@ struct ScoreParams {
   int32_t* ids_out;
   float* scores_out;
   int32_t* short_ids;        // [m][short_ld]
+  float* short_sc;           // [m][short_ld] approximate scores, or null
   int32_t short_ld;
   int64_t* stats;
   uint32_t* gbitmap;         // [gridDim.x][bm_words], zero on entry and on exit
@@ -797,9 +800,11 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         }
       } else {
         int32_t* so = p.short_ids + (size_t)q * p.short_ld;
+        float* ss = p.short_sc ? p.short_sc + (size_t)q * p.short_ld : nullptr;
         for (int r = tid; r < kk; r += kBlock) {
           const uint64_t key = (uint32_t)r < c0 ? cand[r] : 0ull;
           so[r] = key_id(key);
+          if (ss) ss[r] = (uint32_t)r < c0 ? key_score(key) : -INFINITY;
         }
       }
       if (tid == 0 && p.stats) {
@@ -836,23 +841,51 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
 
 // Exact float32 rerank of a short list (one 256-thread block per query); the same lane layout
 // and reduction tree as the FP32 scoring pass, so a reranked score equals the FP32-path score.
+// With bound_c > 0 (every row's approximate score is within bound_c * ||q|| of its FP32 score,
+// and the list is in descending approximate order), rows from the first one past position k - 1
+// whose approximate score is below a(k-1) - 2 bound_c ||q|| are not rescored: each of them scores
+// below a(k-1) - bound_c ||q||, and so below the k listed rows before it, so the top k is the
+// same as over the whole list.
 template <int G, int C>
 __global__ __launch_bounds__(256) void rerank_kernel(
     const float* __restrict__ X, int64_t ldx, int nchunks, int d, const float* __restrict__ Q,
-    int ldq, int64_t m, const int32_t* __restrict__ short_ids, int short_ld,
-    const int32_t* __restrict__ k_arr, int k_uniform, int R_opt, const int64_t* __restrict__ out_off,
-    int32_t* __restrict__ ids_out, float* __restrict__ scores_out) {
+    int ldq, int64_t m, const int32_t* __restrict__ short_ids, const float* __restrict__ short_sc,
+    int short_ld, float bound_c, const int32_t* __restrict__ k_arr, int k_uniform, int R_opt,
+    const int64_t* __restrict__ out_off, int32_t* __restrict__ ids_out,
+    float* __restrict__ scores_out) {
   constexpr int RPI = 64 / G;
   __shared__ uint64_t key[kMaxK];
+  __shared__ int s_cut;
   const int64_t q = blockIdx.x;
   if (q >= m) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane % G, sub = lane / G;
   const int k = k_arr ? k_arr[q] : k_uniform;
-  const int R = short_len(R_opt, k);
+  int R = short_len(R_opt, k);
   float qv[C][4];
   load_query<FPP_STORE_FP32, G, C>(Q + q * ldq, d, g, qv);
   const int32_t* sl = short_ids + (size_t)q * short_ld;
+  if (bound_c > 0.0f && short_sc && R > k) {
+    // ||q||: the G lanes of a row group hold all of q; the factor covers the rounding of the sum
+    // of squares and of the root, so qn >= ||q||
+    float ss = 0.0f;
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) ss = fmaf(qv[c][e], qv[c][e], ss);
+    const float qn = sqrtf(tree_sum<G>(ss)) * 1.0000152587890625f;
+    const float* sa = short_sc + (size_t)q * short_ld;
+    const float ak = sa[k - 1];
+    const float b2 = 2.0f * bound_c * qn;
+    // the last term covers the rounding of b2 and of the subtraction
+    const float t = ak - b2 - (fabsf(ak) + b2) * 2.384185791015625e-07f;   // 2^-22
+    if (tid == 0) s_cut = R;
+    __syncthreads();
+    for (int r = k + tid; r < R; r += 256)
+      if (!(sa[r] >= t)) atomicMin(&s_cut, r);
+    __syncthreads();
+    R = s_cut;
+  }
   const int Rp2 = sort_size((uint32_t)R);
   for (int r0 = 0; r0 < Rp2; r0 += 4 * RPI) {
     const int r = r0 + wave * RPI + sub;
@@ -919,6 +952,18 @@ int score_grid_blocks(const fpp_index* ix) {
   return (cus > 0 ? cus : 256) * kBlocksPerCU;
 }
 
+// |approximate - FP32 score| for a BF16 row: the rounding of x to BF16 (at most 2^-9 |x_j|) and
+// the float32 rounding of the two sums (chains of at most d + 16 steps, gamma = (d + 16) u /
+// (1 - (d + 16) u), u = 2^-24, for each), against sum_j |q_j x_j| <= ||q|| ||x||:
+// (2^-9 + 2.01 gamma) ||q|| max_i ||x_i||, rounded up.
+float bf16_rerank_bound(const fpp_index* ix) {
+  if (!(ix->xnorm_max > 0.0f)) return -1.0f;
+  const double u = std::ldexp(1.0, -24), mm = (double)ix->d + 16.0;
+  const double gamma = mm * u / (1.0 - mm * u);
+  const double c = (std::ldexp(1.0, -9) + 2.01 * gamma) * (double)ix->xnorm_max * (1.0 + 1e-6);
+  return std::nextafter((float)c, INFINITY);
+}
+
 hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) {
   if (a.m <= 0) return hipSuccess;
   if (!a.gbitmap) return hipErrorInvalidValue;
@@ -946,6 +991,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.work = a.gbitmap + (size_t)a.grid * (size_t)sp.bm_words;   // after the bitmaps
   sp.zero16 = reinterpret_cast<const unsigned char*>(sp.work + 4);   // never written
   sp.short_ids = a.short_ids;
+  sp.short_sc = a.short_sc;
   sp.short_ld = a.short_ld;
   sp.lowp = (a.store == FPP_STORE_FP32 || a.rerank_R < 0) ? 0 : 1;
   sp.R_opt = a.rerank_R;
@@ -988,15 +1034,16 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
 }
 
 hipError_t launch_rerank(const fpp_index* ix, const float* Q, int ldq, int64_t m,
-                         const int32_t* short_ids, int short_ld, const int32_t* k_arr,
-                         int k_uniform, int R_opt, const int64_t* out_off, int32_t* ids_out,
-                         float* scores_out, hipStream_t s) {
+                         const int32_t* short_ids, const float* short_sc, int short_ld,
+                         float bound_c, const int32_t* k_arr, int k_uniform, int R_opt,
+                         const int64_t* out_off, int32_t* ids_out, float* scores_out,
+                         hipStream_t s) {
   if (m <= 0) return hipSuccess;
   const int nc = ix->ldx / 4;
 #define FPP_RERANK(GG, CC)                                                                      \
   hipLaunchKernelGGL((rerank_kernel<GG, CC>), dim3((unsigned)m), dim3(256), 0, s, ix->X,       \
-                     (int64_t)ix->ldx, nc, ix->d, Q, ldq, m, short_ids, short_ld, k_arr,        \
-                     k_uniform, R_opt, out_off, ids_out, scores_out)
+                     (int64_t)ix->ldx, nc, ix->d, Q, ldq, m, short_ids, short_sc, short_ld,     \
+                     bound_c, k_arr, k_uniform, R_opt, out_off, ids_out, scores_out)
   if (nc <= 8) FPP_RERANK(8, 1);      // the FP32 gather's (G, C) for the same chunk count
   else if (nc <= 16) FPP_RERANK(8, 2);
   else if (nc <= 32) FPP_RERANK(8, 4);
