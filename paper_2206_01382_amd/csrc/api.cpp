@@ -550,6 +550,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
     a.short_ids = shortl;
     a.short_sc = shortsc;
     a.short_ld = ly.short_ld;
+    a.cut_c = qs.R_opt >= 0 ? bound_c : -1.0f;
     int32_t* ids_c = qs.ids_out;
     float* sc_c = qs.scores_out;
     const int64_t* off_c = nullptr;

@@ -190,6 +190,8 @@ struct ScoreArgs {
   int32_t* short_ids;      // [m][short_ld] short lists (low-precision stores)
   float* short_sc;         // [m][short_ld] their approximate scores (-inf past the list)
   int32_t short_ld;
+  float cut_c;             // > 0: the rerank's bound constant (launch_rerank); the gather then
+                           // also drops candidates that the rerank could not keep
   int64_t* stats;          // [m][3] or null
   uint32_t* gbitmap;       // overflow dedup bitmaps [grid][ceil(n/32)], zero on entry and exit
   int32_t grid;            // persistent blocks

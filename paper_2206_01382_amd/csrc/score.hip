@@ -340,6 +340,7 @@ struct ScoreParams {
   int32_t* short_ids;        // [m][short_ld]
   float* short_sc;           // [m][short_ld] approximate scores, or null
   int32_t short_ld;
+  float cut_c;               // > 0: bound constant of the rerank's cut (see rerank_kernel)
   int64_t* stats;
   uint32_t* gbitmap;         // [gridDim.x][bm_words], zero on entry and on exit
   uint32_t* work;            // [2]: next query, finished workgroups; zero on entry and on exit
@@ -427,6 +428,18 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     const int kk = p.lowp ? short_len(p.R_opt, k) : k;   // list length kept by this pass
     float qv[C][EPC];
     load_query<STORE, G, C>(p.Q + q * p.ldq, p.d, g, qv);
+    // with a rerank cut (see rerank_kernel): 2 * its bound for this query, else 0
+    float cut_b2 = 0.0f;
+    if constexpr (STORE == FPP_STORE_BF16) {
+      if (p.cut_c > 0.0f) {
+        float ss = 0.0f;
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+          for (int e = 0; e < EPC; ++e) ss = fmaf(qv[c][e], qv[c][e], ss);
+        cut_b2 = 2.0f * p.cut_c * (sqrtf(tree_sum<G>(ss)) * 1.0000152587890625f);
+      }
+    }
     if (tid == 0) {
       st->qcount = 0;
       st->ccount = 0;
@@ -436,7 +449,10 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
     }
     __syncthreads();
 
-    // keep the best kk candidates (sorted) and raise the threshold
+    // keep the best kk candidates (sorted) and raise the threshold. With a rerank cut the
+    // threshold is at least the k-th best approximate score so far minus 2 * the bound: a later
+    // candidate below it scores below the final short list's k-th approximate score minus that,
+    // which the rerank would not rescore, so the result does not change
     auto compact = [&]() {
       const uint32_t c0 = st->ccount;
       const int n = sort_size(c0);
@@ -446,7 +462,18 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
       block_sort_desc(cand, n);
       if (tid == 0) {
         st->ccount = c0 < (uint32_t)kk ? c0 : (uint32_t)kk;
-        if (c0 >= (uint32_t)kk) st->thr = cand[kk - 1];
+        uint64_t thr = st->thr;
+        if (c0 >= (uint32_t)kk) thr = cand[kk - 1];
+        if (cut_b2 > 0.0f && c0 >= (uint32_t)k) {
+          const float a = key_score(cand[k - 1]);
+          // the last term covers the rounding of the subtraction
+          const float t2 = a - cut_b2 - (fabsf(a) + cut_b2) * 2.384185791015625e-07f;   // 2^-22
+          const uint32_t u = __float_as_uint(t2 + 0.0f);
+          const uint32_t ord = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+          const uint64_t thr2 = ((uint64_t)ord << 32) - 1ull;   // every key scoring >= t2 passes
+          thr = thr2 > thr ? thr2 : thr;
+        }
+        st->thr = thr;
       }
       __syncthreads();
     };
@@ -993,6 +1020,7 @@ hipError_t launch_score(const fpp_index* ix, const ScoreArgs& a, hipStream_t s) 
   sp.short_ids = a.short_ids;
   sp.short_sc = a.short_sc;
   sp.short_ld = a.short_ld;
+  sp.cut_c = a.cut_c;
   sp.lowp = (a.store == FPP_STORE_FP32 || a.rerank_R < 0) ? 0 : 1;
   sp.R_opt = a.rerank_R;
   const int grid = a.grid;
