@@ -16,8 +16,8 @@
 //      and a fixed xor-shuffle tree over the G lanes finishes the sum. Scores therefore do not
 //      depend on batching or on which workgroup computes them.
 //   C. candidates above the running kk-th best key go to an LDS buffer that is sorted and cut to
-//      the best kk once it holds more than max(3 kk, 192); the final sort gives (score desc,
-//      id asc) order.
+//      the best kk once it holds more than 255 (kk <= 128; else 3 kk); the final sort gives
+//      (score desc, id asc) order.
 // Keys are 64-bit: order-preserving float bits << 32 | (0xffffffff - id).
 // The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
 // scores exactly in float32 from the FP32 store.
@@ -558,10 +558,11 @@ __global__ __launch_bounds__(kBlock) void score_kernel(ScoreParams p) {
         }
         __syncthreads();
         const bool fin = last && sb + PPC * RPB >= rows;
-        // compact once the buffer holds more than max(3 kk, 192) entries: the threshold rises
-        // early enough that most later rows are rejected without a store, and at BF16's kk = 100
-        // a query needs about two sorts (a trigger of 2 kk took three and ran 8% slower)
-        uint32_t trig = (uint32_t)(3 * kk > 192 ? 3 * kk : 192);
+        // compact once the buffer holds more than 255 entries (kk <= 128; else 3 kk): the first
+        // sync group's rows then sort as one 256-key block, the threshold rises early enough that
+        // most later rows are rejected without a store (with the rerank cut's threshold, nearly
+        // all), and a query needs about two sorts (a trigger of 200 took three at kk = 100)
+        uint32_t trig = (uint32_t)(kk <= 128 ? 255 : 3 * kk);
         if (trig > (uint32_t)(kCandCap - PPC * RPB)) trig = (uint32_t)(kCandCap - PPC * RPB);
         if (fin || st->ccount > trig) compact();
       }
