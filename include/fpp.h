@@ -350,6 +350,14 @@ int fpp_debug_export_store(const fpp_index* index, int32_t store, void* codes_ou
  * against running queries on the index. Errors: FPP_EINVAL. */
 int fpp_debug_set_partition_threshold(fpp_index* index, int64_t min_entries, int32_t range_bits);
 
+/* For tests of the BF16 rerank: with a BF16 store, the rerank rescores only the head of a short
+ * list that can still reach the top k (rows below the k-th approximate score by more than twice
+ * a bound on |approximate - FP32 score| cannot), and the gather drops such candidates as it
+ * scores; the results are the same as rescoring every listed row. enabled = 0 turns both off
+ * (every short-listed row is rescored), 1 (the default) on. Not thread-safe against running
+ * queries on the index. Errors: FPP_EINVAL. */
+int fpp_debug_set_rerank_cut(fpp_index* index, int32_t enabled);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,7 @@ from ._lib import (  # noqa: F401
     FPP_STORE_FP8, FPP_FILTER_FRACTION, FPP_FILTER_THRESHOLD, FPP_PROBE_GAP, FPP_PROBE_SUM, FppError,
     LIB_PATH, fpp_build_index,
     fpp_debug_build_records, fpp_debug_center, fpp_debug_export_store, fpp_normal_quantile,
-    fpp_debug_set_partition_threshold,
+    fpp_debug_set_partition_threshold, fpp_debug_set_rerank_cut,
     fpp_debug_export_table, fpp_debug_probes, fpp_debug_query_lists, fpp_debug_signs, fpp_free_index,
     fpp_index_get_info, fpp_index_table_sizes, fpp_last_error, fpp_query, fpp_query_batch, fpp_query_ex_noalloc,
     fpp_query_workspace_bytes, fpp_server_create, fpp_server_debug_fail_batches, fpp_server_destroy,

@@ -106,6 +106,7 @@ SIGNATURES = {
     "fpp_debug_export_store": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "fpp_debug_center": (c_i32, [c_vp, c_vp]),
     "fpp_debug_set_partition_threshold": (c_i32, [c_vp, c_i64, c_i32]),
+    "fpp_debug_set_rerank_cut": (c_i32, [c_vp, c_i32]),
     "fpp_normal_quantile": (ctypes.c_double, [ctypes.c_double]),
 }
 
@@ -311,6 +312,11 @@ def fpp_debug_set_partition_threshold(h, min_entries: int, range_bits: int = -1)
     """Queries with more probed entries than min_entries are deduplicated by id range, in ranges
     of 2^range_bits ids (< 0: the defaults)."""
     _check(lib().fpp_debug_set_partition_threshold(h, int(min_entries), int(range_bits)))
+
+
+def fpp_debug_set_rerank_cut(h, enabled: bool) -> None:
+    """Turn the BF16 rerank's cut (and the gather's matching threshold) off or on."""
+    _check(lib().fpp_debug_set_rerank_cut(h, 1 if enabled else 0))
 
 
 def fpp_normal_quantile(p: float) -> float:

@@ -501,7 +501,7 @@ int run_queries(const fpp_index* ix, const QuerySpec& qs, const Layout& ly,
   int32_t* np = (int32_t*)(ws + ly.off_np);
   int32_t* shortl = (int32_t*)(ws + ly.off_short);
   float* shortsc = (float*)(ws + ly.off_short) + (size_t)ly.mc * ly.short_ld;
-  const float bound_c = qs.store == FPP_STORE_BF16 ? bf16_rerank_bound(ix) : -1.0f;
+  const float bound_c = qs.store == FPP_STORE_BF16 && ix->rerank_cut ? bf16_rerank_bound(ix) : -1.0f;
   uint32_t* gbm = ly.gbm ? (uint32_t*)(ws + ly.off_gbm) : qs.gbm_ext;
   const int d = ix->d;
   for (int64_t c0 = 0; c0 < qs.m; c0 += ly.mc) {
@@ -921,6 +921,13 @@ int fpp_debug_set_partition_threshold(fpp_index* ix, int64_t min_entries, int32_
     return set_error("range_bits=%d out of [5, %d]", range_bits, fpp_index::kPartShiftDefault), FPP_EINVAL;
   ix->part_min = min_entries < 0 ? fpp_index::kPartMinDefault : min_entries;
   ix->part_shift = range_bits < 0 ? fpp_index::kPartShiftDefault : range_bits;
+  return FPP_OK;
+}
+
+int fpp_debug_set_rerank_cut(fpp_index* ix, int32_t enabled) {
+  if (!ix) return set_error("index is NULL"), FPP_EINVAL;
+  if (enabled != 0 && enabled != 1) return set_error("enabled=%d: 0 or 1", enabled), FPP_EINVAL;
+  ix->rerank_cut = enabled == 1;
   return FPP_OK;
 }
 

@@ -65,6 +65,7 @@ struct fpp_index {
   uint8_t* Xfp8 = nullptr;        // device [n][ld8]
   float* fp8_scale = nullptr;     // device [n]
   float xnorm_max = -1.0f;        // an upper bound of the rows' L2 norms (BF16 builds), else -1
+  bool rerank_cut = true;         // the BF16 rerank's cut (fpp_debug_set_rerank_cut)
   float* center_vec = nullptr;    // device [d] centring vector (centred builds only)
   uint32_t* Xsig = nullptr;       // device [n][ldsig] SimHash signatures
   int32_t sigF = 0;               // hash functions in a signature

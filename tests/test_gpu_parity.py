@@ -741,6 +741,58 @@ def test_maximum_sizes_k512_rerank512(store):
     assert swaps <= swap_budget(ids.numel()), swaps
 
 
+def _near_duplicate_sphere(groups, per, d, m, seed):
+    """Groups of near-duplicate unit vectors (8e-3 per coordinate around a random unit direction)
+    and queries near some of the directions: a group's scores spread over about 2.6e-3, less than
+    twice the rerank's bound (about 3.9e-3 at d = 64), so the cut's boundary falls among them,
+    while their gaps (at least about 4e-7 here) stay above float32 rounding."""
+    rng = np.random.default_rng(seed)
+    base = rng.standard_normal((groups, d))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    X = np.repeat(base, per, axis=0) + 8e-3 * rng.standard_normal((groups * per, d))
+    X /= np.linalg.norm(X, axis=1, keepdims=True)
+    Q = base[:m] + 1e-2 * rng.standard_normal((m, d))
+    Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    return X.astype(np.float32), Q.astype(np.float32)
+
+
+@pytest.mark.parametrize("name", ["l2_clustered", "p512_d300_D256", "fused_d128_D128", "near_duplicates"])
+def test_rerank_cut_changes_nothing(name):
+    """BF16 + rerank with the cut (only the rows that can still reach the top k are rescored, and
+    the gather drops the others as it scores) against rescoring every short-listed row: equal ids
+    and scores, bit for bit, for several k and short-list lengths; and equal to the oracle."""
+    own = name == "near_duplicates"
+    if own:
+        X, Q = _near_duplicate_sphere(200, 20, 64, 30, seed=5)
+        Xd = torch.from_numpy(X).cuda()
+        h = F().fpp_build_index(Xd, 4, 64, 0.5, 3, SEED, l=2, stores=("bf16",))
+        Qd = torch.from_numpy(Q).cuda()
+        L = 4
+    else:
+        w, oi, h, Xd, Qd = built(name)
+        X, Q, L = w["X"], w["Q"], w["L"]
+    try:
+        qp = 8 * L
+        for k, R in ((1, 0), (10, 0), (10, 30), (50, 0), (50, 150)):
+            F().fpp_debug_set_rerank_cut(h, True)
+            ids_c, sc_c = F().fpp_query(h, Qd, k, qp, store="bf16", rerank_R=R)
+            F().fpp_debug_set_rerank_cut(h, False)
+            ids_f, sc_f = F().fpp_query(h, Qd, k, qp, store="bf16", rerank_R=R)
+            assert torch.equal(ids_c, ids_f), (k, R)
+            assert torch.equal(sc_c.view(torch.int32), sc_f.view(torch.int32)), (k, R)
+        if own:
+            oi = O.build_index(X, 4, 64, 0.5, 3, SEED, l=2)
+        F().fpp_debug_set_rerank_cut(h, True)
+        ids, sc = F().fpp_query(h, Qd, 10, qp, store="bf16")
+        oids, osc, _ = O.query_reranked(oi, Q, 10, qp, R=100, storage="bf16")
+        swaps = check_topk(X, Q, ids.cpu().numpy(), sc.cpu().numpy(), oids, osc)
+        assert swaps <= swap_budget(ids.numel()), swaps
+    finally:
+        F().fpp_debug_set_rerank_cut(h, True)
+        if own:
+            F().fpp_free_index(h)
+
+
 def test_rerank_of_exactly_k_is_a_reorder_with_exact_scores():
     """With R = k the rerank reorders the approximate top-k; its scores are exact FP32 dot
     products of the original rows (float64 within the FP32 accumulation bound)."""
