@@ -8,9 +8,9 @@
 //      (set semantics: an id is scored once however many buckets hold it). Past 3072 distinct
 //      ids the workgroup moves the set into its n-bit bitmap in device memory and continues
 //      there. First-time ids enter an LDS queue. A query with more than 16,384 entries (by
-//      default; they must fit the workgroup's bitmap region as a buffer) is deduplicated by id range instead: its
-//      ids are grouped by id >> 18 into that buffer and each group is tested against an LDS
-//      bitmap of its 2^18 ids.
+//      default; they must fit the workgroup's bitmap region as a buffer) is deduplicated by id
+//      range instead: its ids are grouped by id >> 18 into that buffer and each group is tested
+//      against an LDS bitmap of its 2^18 ids.
 //   B. when the queue holds >= 1024 ids (and at the end) the waves score it: G lanes cover one
 //      row with 16-byte loads, each lane folds its chunks into a float32 partial in a fixed order,
 //      and a fixed xor-shuffle tree over the G lanes finishes the sum. Scores therefore do not
@@ -19,8 +19,9 @@
 //      the best kk once it holds more than 255 (kk <= 128; else 3 kk); the final sort gives
 //      (score desc, id asc) order.
 // Keys are 64-bit: order-preserving float bits << 32 | (0xffffffff - id).
-// The low-precision stores (BF16, FP8) produce a short list of R ids that the rerank kernel
-// scores exactly in float32 from the FP32 store.
+// The low-precision stores (BF16, FP8) produce a short list of R ids (and their approximate
+// scores) that the rerank kernel scores exactly in float32 from the FP32 store. For BF16 both
+// kernels also drop what provably cannot reach the final top k (rerank_kernel states the bound).
 #include <cmath>
 
 #include "fpp_internal.hpp"
